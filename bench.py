@@ -1,0 +1,177 @@
+"""Benchmark of the fluctuating lattice Boltzmann step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload (one "step" = one pass of the hot path over the lattice): a D2Q5
+lattice of 4096 x 4096 sites, float32 populations, mean density 10 with a
+sine mode of relative amplitude 0.1, omega = 1, local Gaussian noise, seed 0;
+every step runs the fused stream-collide kernel, and every `--sample-every`
+steps (default 10) the FP64 lattice sums and the structure factor of 1024
+axis modes are accumulated on the device.  Prints one JSON line.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--sample-every", type=int, default=10)
+    ap.add_argument("--size", type=int, default=4096)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    return ap.parse_args()
+
+
+def workload_state(flb, inputs, n, precision):
+    w, _ = flb.constants(2)
+    rho = inputs.sine_field((n, n), 10.0, 0.1)
+    return inputs.outer(w, rho).astype(np.float32 if precision == 4 else np.float64)
+
+
+def time_steps(torch, L, steps, sample_every, kvecs):
+    """Run `steps` steps; return wall ms/step and the mean step-kernel
+    duration from events recorded around every step launch on the
+    lattice's stream."""
+    st = L.stream
+    pre = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    post = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        pre[i].record(st)
+        L.step(1)
+        post[i].record(st)
+        if sample_every and (i + 1) % sample_every == 0:
+            L.structure_factor(kvecs, mode="sample")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = float(np.mean([a.elapsed_time(b) for a, b in zip(pre, post)]))
+    return (t1 - t0) * 1e3 / steps, kern
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the lattice would shard by slabs with a one-layer halo exchange per step). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(1)
+    import torch
+    from paper_1606_07801_amd import flb, inputs, tune
+
+    torch.cuda.set_device(0)
+    n = args.size
+    dims = (n, n)
+    N = n * n
+    Q = 5
+    cfg = tune.best_config(2, 4, dims)
+    f0 = workload_state(flb, inputs, n, 4)
+    L = flb.Lattice(2, dims, precision=4, omega=1.0, seed=0, noise="local", **cfg)
+    L.set_populations(f0)
+    kvecs = [(k, 0) for k in range(1, 513)] + [(0, k) for k in range(1, 513)]
+    L.structure_factor(kvecs, mode="reset")
+
+    # warmup, then the timed region (all hot-path rows: step + sampled stats)
+    for i in range(args.warmup):
+        L.step(1)
+        if args.sample_every and (i + 1) % args.sample_every == 0:
+            L.structure_factor(kvecs, mode="sample")
+    ms_step, kern_ms = time_steps(torch, L, args.steps, args.sample_every, kvecs)
+    m = L.moments()
+    S = L.structure_factor(None, mode="read")[:len(kvecs)]
+    L.close()
+
+    value = N / (ms_step * 1e-3) / 1e6  # MLUPS of the whole job
+    bytes_per_launch = 2 * Q * 4 * N   # algorithmic: read and write every population once
+    achieved = bytes_per_launch / (kern_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": "MLUPS", "value": round(value, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"D2Q5 {n}x{n} periodic, fp32 populations, rho=10 sine mode 0.1, "
+                        f"omega=1.0, local Gaussian noise (Philox), lattice sums + S(k) of 1024 axis "
+                        f"modes sampled every {args.sample_every} steps",
+            "kernel": cfg, "sites": N,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "kernel": "k_step_rows<2,float>", "kernel_us": round(kern_ms * 1e3, 2),
+            "bytes_per_launch": bytes_per_launch,
+        },
+        "step_kernel_mlups": round(N / (kern_ms * 1e-3) / 1e6, 1),
+        "mass_drift_rel": abs(m["mass"] - m["mass0"]) / m["mass0"],
+        "sk_mean_over_rho": float(np.mean(S) / m["rho_eq"]),
+    }
+
+    if not args.no_fp64:
+        # comparator: the plain FP64 single-lattice path on the same GPU
+        f64 = workload_state(flb, inputs, n, 8)
+        P = flb.Lattice(2, dims, precision=8, omega=1.0, seed=0, kernel="plain")
+        P.set_populations(f64)
+        P.step(10)
+        k64 = max(args.steps // 4, 20)
+        ms64, kern64 = time_steps(torch, P, k64, 0, None)
+        P.close()
+        out["fp64_plain"] = {"mlups": round(N / (ms64 * 1e-3) / 1e6, 1), "ms_per_step": round(ms64, 4),
+                             "hbm_gbs": round(2 * Q * 8 * N / (kern64 * 1e-3) / 1e9, 1)}
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(flb, inputs, n, f0)
+
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(flb, inputs, n, f0):
+    """The FP64 oracle (single-threaded numpy) on a bounded sample of the
+    same workload: 2 steps of the full lattice from the seeded state.  The
+    GPU path's 2-step result from the same state is compared with it."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    import oracle
+
+    nsteps = 2
+    p = oracle.Params(d=2, omega_j=1.0, seed=0, noise="local")
+    lat = p.lattice()
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    t0 = time.perf_counter()
+    if ctx:
+        with ctx:
+            ref = oracle.run(f0.astype(np.float64), p, nsteps, lat=lat)
+    else:
+        ref = oracle.run(f0.astype(np.float64), p, nsteps, lat=lat)
+    dt = time.perf_counter() - t0
+    L = flb.Lattice(2, (n, n), precision=4, omega=1.0, seed=0, noise="local")
+    L.set_populations(f0)
+    L.step(nsteps)
+    g = L.get_populations()
+    L.close()
+    floor = (10.0 * lat.w).reshape(-1, 1, 1)
+    err = float((np.abs(g.astype(np.float64) - ref) / np.maximum(np.abs(ref), floor)).max())
+    return {"value": round(nsteps * n * n / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{nsteps} steps of the {n}x{n} D2Q5 lattice from the seeded state ({dt:.1f} s)",
+            "gpu_fp32_max_err_vs_oracle": err}
+
+
+if __name__ == "__main__":
+    main()

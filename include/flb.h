@@ -1,0 +1,193 @@
+/*
+ * flb.h - C ABI of the MI355X (gfx950) fluctuating lattice Boltzmann library
+ * for the diffusion equation (Wagner & Strand, "A Fluctuating Lattice
+ * Boltzmann Method for the Diffusion Equation", arXiv:1606.07801).
+ *
+ * The method (paper Sec. II):
+ *   f_i(x + v_i, t + 1) = f_i(x, t) + Omega_i                         eq. (LB)
+ *   Omega_i = sum_j Lambda_ij (f_j^0 - f_j) + xi_i                    eq. (collision)
+ * with f_i^0 = rho w_i (eq. f0def), a collision matrix that is diagonal in
+ * the orthonormal moment basis m_i^a (Sec. II, Gram-Schmidt under
+ * sum_i m_i^a w_i m_i^b = delta^ab), relaxation rate omega_a = 1/tau^a per
+ * isotropy class, and noise on the non-conserved moments only, with variance
+ *   <xi^a xi^a> = rho_n (2 tau^a - 1) / (tau^a)^2                     eqs. (xilocal), (xiglobal)
+ * where rho_n is the local density clamped at zero (Sec. IV, closing the
+ * algorithm), the global mean density, or zero (noise off).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Lattices: D1Q3, D2Q5, D3Q7 on a periodic box n[0] x n[1] x n[2]
+ *   (unused sizes are 1).  Velocity order: 0, +x, -x, +y, -y, +z, -z.
+ * - Canonical state: the pre-collision populations f_i(x, t) in SoA layout
+ *   f[i][z][y][x] (x fastest), in the lattice's precision (4 = float32,
+ *   8 = float64).  The site index is s = x + n0 (y + n1 z).
+ * - Noise: Philox4x32-10 keyed by the 64-bit seed (low word, high word),
+ *   counter (s low word, s high word, t mod 2^32, block) with t the number
+ *   of steps completed before the collision and block = (a - 1) / 4 for
+ *   moment a >= 1; moment a takes word (a - 1) mod 4 of its block.  Words map
+ *   to u = (2 (r >> 9) + 1) 2^-24, and pairs of u to normals by Box-Muller
+ *   (R = sqrt(-2 ln u0), z0 = R cos 2 pi u1, z1 = R sin 2 pi u1).  The
+ *   uniform law uses xi = sqrt(3 var) (2u - 1) (the paper's flat law, Sec. IV).
+ * - Memory: the caller owns every device buffer and the HIP stream; the
+ *   library owns the opaque handle, an optional workspace it allocates when
+ *   the caller passes none, and small pinned staging.  Calls on one handle
+ *   are not thread-safe; each handle issues all of its work on its stream.
+ * - Errors: every function returns 0 (FLB_OK) or a negative FLB_E* code and
+ *   leaves a message for flb_last_error() (thread-local).  Nothing throws
+ *   across the ABI.  A failed call leaves the handle's state unchanged,
+ *   except FLB_EDEVICE, after which the handle should be destroyed.
+ */
+#ifndef FLB_H
+#define FLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FLB_ABI_VERSION 1
+
+enum {
+  FLB_OK = 0,
+  FLB_EINVAL = -1,      /* invalid argument or parameter */
+  FLB_ENOMEM = -2,      /* buffer too small, or allocation failed */
+  FLB_EDEVICE = -3,     /* HIP runtime error */
+  FLB_ESTATE = -4,      /* call not valid in the handle's current state */
+  FLB_ENONFINITE = -5   /* non-finite populations detected (check mode) */
+};
+
+enum { FLB_D1Q3 = 1, FLB_D2Q5 = 2, FLB_D3Q7 = 3 };
+enum { FLB_NOISE_LOCAL = 0, FLB_NOISE_GLOBAL = 1, FLB_NOISE_OFF = 2 };
+enum { FLB_LAW_GAUSS = 0, FLB_LAW_UNIFORM = 1 };
+/* storage scheme: two buffers with pull streaming (the only one so far) */
+enum { FLB_LAYOUT_TWO_BUFFER = 0 };
+/* kernel variants of the step (all give bit-identical results) */
+enum { FLB_KERNEL_AUTO = 0, FLB_KERNEL_PLAIN = 1, FLB_KERNEL_ROWS = 2 };
+
+typedef struct flb_lattice flb_lattice; /* opaque */
+
+typedef struct {
+  int32_t model;      /* FLB_D1Q3 / FLB_D2Q5 / FLB_D3Q7 */
+  int32_t precision;  /* 4 = float32 populations, 8 = float64 */
+  int64_t n[3];       /* box sizes (n[1], n[2] = 1 below 2-D / 3-D); each >= 1 */
+  double theta;       /* lattice temperature; 0 -> 1/3 (D1Q3, D2Q5), 1/4 (D3Q7);
+                         must satisfy 0 < theta < 1/d */
+  double omega[3];    /* relaxation rates of the current (j), traceless (n) and
+                         trace (s) moments, each in (0, 2); omega[1], omega[2]
+                         = 0 -> omega[0].  D = (1/omega_j - 1/2) theta. */
+  uint64_t seed;      /* Philox key */
+  int32_t noise;      /* FLB_NOISE_* */
+  int32_t noise_law;  /* FLB_LAW_* */
+  int32_t layout;     /* FLB_LAYOUT_* */
+  int32_t kernel;     /* FLB_KERNEL_* */
+  int32_t tile_x;     /* rows kernel: threads per block along x (64..1024, multiple
+                         of 64); 0 -> default */
+  int32_t tile_rows;  /* rows kernel: rows per thread (1..16); 0 -> default */
+} flb_params;
+
+typedef struct {
+  int64_t step;          /* steps completed */
+  int64_t nsite;
+  double mass;           /* sum_x rho */
+  double mass0;          /* mass when the populations were last set */
+  double rho_eq;         /* mass0 / nsite: the global-noise density */
+  double sum_f[7];       /* sum_x f_i (first Q used) */
+  double sum_ff[28];     /* sum_x f_i f_j, i <= j, packed row-major upper triangle */
+  double sum_rho2;       /* sum_x rho^2 */
+  double sum_rho_pos;    /* sum_x max(rho, 0) */
+  int64_t n_negative;    /* number of sites with rho < 0 */
+  int64_t nonfinite;     /* number of non-finite populations */
+} flb_moments_t;
+
+/* flb_structure_factor modes */
+enum {
+  FLB_SK_SNAPSHOT = 0, /* S_out[n] = |rho(k_n)|^2 / N of the current state */
+  FLB_SK_SAMPLE = 1,   /* add the current state's values to the accumulator (async) */
+  FLB_SK_READ = 2,     /* S_out[n] = accumulated mean over samples */
+  FLB_SK_RESET = 3     /* clear the accumulator and adopt kvec as its k-list */
+};
+
+/* Library ABI version (FLB_ABI_VERSION). */
+int flb_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* flb_last_error(void);
+
+/* The library's own equilibrium weights w (Q values) and moment basis m
+ * (Q x Q, row a = moment, column i = population) for a model and theta
+ * (0 -> default), paper Sec. II.  Host pointers; either may be NULL.
+ * Returns Q (> 0) or FLB_EINVAL. */
+int flb_lattice_constants(int32_t model, double theta, double* w, double* m);
+
+/* Bytes of caller-provided device memory a lattice needs: pop_bytes for the
+ * populations (one or two buffers of Q * N * precision bytes) and
+ * work_bytes for the workspace (reductions, structure-factor marginals and
+ * accumulators).  Validates the parameters. */
+int flb_required_bytes(const flb_params* p, size_t* pop_bytes, size_t* work_bytes);
+
+/* Create a lattice on the current HIP device.  d_pop (>= pop_bytes, 256-byte
+ * aligned) holds the populations; d_work (>= work_bytes) the workspace, or
+ * NULL to let the library allocate it.  hip_stream is a hipStream_t (NULL =
+ * the null stream).  The populations are undefined until
+ * flb_set_populations.  On success *out receives the handle. */
+int flb_create(const flb_params* p, void* d_pop, size_t pop_bytes, void* d_work,
+               size_t work_bytes, void* hip_stream, flb_lattice** out);
+
+/* Load the canonical state (Q x N values of the lattice's precision; host or
+ * device memory per src_on_device) and set the step counter to `step`.
+ * Records mass0 and rho_eq (the global-noise density) from the new state.
+ * Synchronises the handle's stream. */
+int flb_set_populations(flb_lattice* h, const void* src, int src_on_device, int64_t step);
+
+/* Copy the canonical state f_i(x, t) into dst (host or device memory).
+ * Synchronises the handle's stream. */
+int flb_get_populations(flb_lattice* h, void* dst, int dst_on_device);
+
+/* Advance nsteps >= 0 time steps: eq. (LB) with eq. (collision) at every
+ * site.  Asynchronous on the handle's stream. */
+int flb_step(flb_lattice* h, int64_t nsteps);
+
+/* Steps completed so far. */
+int flb_get_step(flb_lattice* h, int64_t* step);
+
+/* Lattice sums of the current state in FP64 (Sec. IV: mass, <f_i>,
+ * <f_i f_j>, plus the density variance, clamped mass, negative-density and
+ * non-finite counts).  Deterministic order.  Synchronises the stream. */
+int flb_moments(flb_lattice* h, flb_moments_t* out);
+
+/* Density structure factor S(k) = |sum_x (rho(x) - rho_mean)
+ * exp(-2 pi i sum_a k_a x_a / n_a)|^2 / N for k != 0 and M^2 / N for k = 0
+ * (Sec. IV, Fourier test with the k = 0 correction).  kvec: nk x 3 host int32
+ * wave numbers (k_x, k_y, k_z), any integers (taken modulo n_a); 1 <= nk <=
+ * 1024.  Modes FLB_SK_*.  SNAPSHOT and READ write nk doubles to S_out (host)
+ * and synchronise; SAMPLE and RESET are asynchronous and ignore S_out.
+ * SAMPLE needs the same kvec as the last RESET.  Axis wave vectors (one
+ * nonzero component) are evaluated from FP64 axis marginals; general ones
+ * by a direct FP64 sum. */
+int flb_structure_factor(flb_lattice* h, const int32_t* kvec, int32_t nk, int32_t mode,
+                         double* S_out);
+
+/* Block until the handle's stream has finished. */
+int flb_sync(flb_lattice* h);
+
+/* Destroy the handle (and the workspace if the library allocated it).
+ * Caller memory is never freed.  NULL is accepted. */
+int flb_destroy(flb_lattice* h);
+
+/* The device noise stream, for checking it against other implementations:
+ * for sites site0 .. site0 + nsite - 1 of a `model` lattice at step `step`,
+ * write the Philox words (uint32, nblock x 4 x nsite, nblock = 1 for D1Q3 and
+ * D2Q5 and 2 for D3Q7) to d_words and the Q - 1 unit-variance variates of
+ * `law` (Q - 1 x nsite, of `precision`) to d_vars.  Device pointers; either
+ * may be NULL.  Asynchronous on hip_stream. */
+int flb_noise_sample(int32_t model, int32_t precision, int32_t law, uint64_t seed,
+                     int64_t step, int64_t site0, int64_t nsite, void* d_words, void* d_vars,
+                     void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLB_H */

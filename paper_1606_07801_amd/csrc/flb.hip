@@ -1,0 +1,700 @@
+// C ABI of the fluctuating lattice Boltzmann library (declared in flb.h):
+// parameter validation, lattice handles, launch configuration of the step,
+// lattice sums, structure factor and the noise sampler.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/flb.h"
+#include "flb_internal.hpp"
+#include "flb_kernels.hpp"
+
+using namespace flb;
+
+// ---------------------------------------------------------------------------
+// errors
+namespace flb {
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(FLB_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+}  // namespace flb
+
+#define HIP_TRY(expr)                                \
+  do {                                               \
+    hipError_t e_ = (expr);                          \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// constants of the product side (Sec. II closed forms)
+namespace flb {
+
+double default_theta(int d) { return d == 3 ? 0.25 : 1.0 / 3.0; }
+
+int check_params(const flb_params* p) {
+  if (!p) return fail(FLB_EINVAL, "params is NULL");
+  if (p->model < 1 || p->model > 3) return fail(FLB_EINVAL, "model must be 1 (D1Q3), 2 (D2Q5) or 3 (D3Q7)");
+  if (p->precision != 4 && p->precision != 8) return fail(FLB_EINVAL, "precision must be 4 or 8");
+  const int d = p->model;
+  for (int a = 0; a < 3; ++a) {
+    if (p->n[a] < 1) return fail(FLB_EINVAL, "box size n[%d] = %lld must be >= 1", a, (long long)p->n[a]);
+    if (a >= d && p->n[a] != 1) return fail(FLB_EINVAL, "n[%d] must be 1 for a %d-D model", a, d);
+  }
+  const double n = (double)p->n[0] * (double)p->n[1] * (double)p->n[2];
+  if (n * (2 * d + 1) * p->precision > 9.0e18) return fail(FLB_EINVAL, "lattice too large");
+  const double th = p->theta == 0.0 ? default_theta(d) : p->theta;
+  if (!(th > 0.0 && th < 1.0 / d)) return fail(FLB_EINVAL, "theta = %g outside (0, 1/%d)", th, d);
+  if (!(p->omega[0] > 0.0 && p->omega[0] < 2.0)) return fail(FLB_EINVAL, "omega_j = %g outside (0, 2)", p->omega[0]);
+  for (int a = 1; a < 3; ++a)
+    if (p->omega[a] != 0.0 && !(p->omega[a] > 0.0 && p->omega[a] < 2.0))
+      return fail(FLB_EINVAL, "omega[%d] = %g outside (0, 2)", a, p->omega[a]);
+  if (p->noise < 0 || p->noise > 2) return fail(FLB_EINVAL, "noise must be 0 (local), 1 (global) or 2 (off)");
+  if (p->noise_law < 0 || p->noise_law > 1) return fail(FLB_EINVAL, "noise_law must be 0 (Gauss) or 1 (uniform)");
+  if (p->layout != FLB_LAYOUT_TWO_BUFFER) return fail(FLB_EINVAL, "layout must be FLB_LAYOUT_TWO_BUFFER");
+  if (p->kernel < 0 || p->kernel > 2) return fail(FLB_EINVAL, "kernel must be 0 (auto), 1 (plain) or 2 (rows)");
+  if (p->tile_x != 0 && (p->tile_x < 64 || p->tile_x > 1024 || p->tile_x % 64 != 0))
+    return fail(FLB_EINVAL, "tile_x must be a multiple of 64 in [64, 1024]");
+  if (p->tile_rows != 0 && p->tile_rows != 1 && p->tile_rows != 2 && p->tile_rows != 4 &&
+      p->tile_rows != 8 && p->tile_rows != 16)
+    return fail(FLB_EINVAL, "tile_rows must be 1, 2, 4, 8 or 16");
+  return FLB_OK;
+}
+
+template <typename T>
+KParams<T> make_kparams(const flb_params& p, double rho_eq) {
+  const int d = p.model;
+  const double th = p.theta == 0.0 ? default_theta(d) : p.theta;
+  const double oj = p.omega[0];
+  const double on = p.omega[1] != 0.0 ? p.omega[1] : oj;
+  const double os = p.omega[2] != 0.0 ? p.omega[2] : oj;
+  const double law = p.noise_law == FLB_LAW_UNIFORM ? std::sqrt(3.0) : 1.0;
+  KParams<T> k;
+  k.nx = p.n[0];
+  k.ny = p.n[1];
+  k.nz = p.n[2];
+  k.n = p.n[0] * p.n[1] * p.n[2];
+  k.a = (T)(1.0 / std::sqrt(th));
+  k.b = (T)(1.0 / std::sqrt(2.0 * th));
+  k.e = (T)(1.0 / std::sqrt(6.0 * th));
+  k.c0 = (T)std::sqrt(d * th / (1.0 - d * th));
+  k.c1 = (T)std::sqrt((1.0 - d * th) / (d * th));
+  k.w1 = (T)(th / 2.0);
+  k.om_j = (T)oj;
+  k.om_n = (T)on;
+  k.om_s = (T)os;
+  k.sq_j = (T)(law * std::sqrt(oj * (2.0 - oj)));
+  k.sq_n = (T)(law * std::sqrt(on * (2.0 - on)));
+  k.sq_s = (T)(law * std::sqrt(os * (2.0 - os)));
+  k.rho_eq = (T)rho_eq;
+  k.k0 = (uint32_t)(p.seed & 0xFFFFFFFFull);
+  k.k1 = (uint32_t)(p.seed >> 32);
+  k.noise = p.noise;
+  k.law = p.noise_law;
+  return k;
+}
+template KParams<float> make_kparams<float>(const flb_params&, double);
+template KParams<double> make_kparams<double>(const flb_params&, double);
+
+}  // namespace flb
+
+// ---------------------------------------------------------------------------
+// workspace layout
+namespace {
+
+constexpr int kRedBlocks = 1024;
+constexpr int kMaxK = 1024;
+constexpr int kSkChunks = 256;
+constexpr int kColChunks = 64;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct WorkLayout {
+  size_t red_part, red_out, rowsum, colpart, marg, skpart, total;
+  // two k-list sets: [0] snapshot, [1] accumulator
+  size_t kinfo[2], kv[2], slot_ax[2], slot_gen[2], sval[2];
+  size_t skacc;
+};
+
+WorkLayout work_layout(const flb_params& p) {
+  WorkLayout L{};
+  const int64_t nx = p.n[0], ny = p.n[1], nz = p.n[2];
+  const int64_t nrows = ny * nz;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  L.red_part = take(sizeof(double) * kRedBlocks * kNV);
+  L.red_out = take(sizeof(double) * kNV);
+  if (p.model >= 2) {
+    L.rowsum = take(sizeof(double) * nrows);
+    L.colpart = take(sizeof(double) * std::min<int64_t>(kColChunks, nrows) * nx);
+    L.marg = take(sizeof(double) * (nx + ny + nz));
+  }
+  L.skpart = take(sizeof(double) * 2 * (size_t)kMaxK * kSkChunks);
+  for (int s = 0; s < 2; ++s) {
+    L.kinfo[s] = take(sizeof(int64_t) * 2 * kMaxK);
+    L.kv[s] = take(sizeof(int64_t) * 3 * kMaxK);
+    L.slot_ax[s] = take(sizeof(int32_t) * kMaxK);
+    L.slot_gen[s] = take(sizeof(int32_t) * kMaxK);
+    L.sval[s] = take(sizeof(double) * kMaxK);
+  }
+  L.skacc = take(sizeof(double) * kMaxK);
+  L.total = o;
+  return L;
+}
+
+// staging for k-lists and results (pinned host memory)
+struct KStage {
+  int64_t kinfo[2 * kMaxK];
+  int64_t kv[3 * kMaxK];
+  int32_t slot_ax[kMaxK];
+  int32_t slot_gen[kMaxK];
+  double out[kMaxK];
+  double red[kNV];
+};
+
+}  // namespace
+
+struct flb_lattice {
+  flb_params p;
+  int d, Q;
+  int64_t n;
+  size_t s;           // bytes per real
+  size_t plane;       // bytes of one buffer (Q * n * s)
+  char* pop;          // two buffers
+  int cur;            // buffer holding the current state
+  char* work;
+  bool own_work;
+  WorkLayout wl;
+  hipStream_t stream;
+  int device;
+  int64_t step;
+  double mass0, rho_eq;
+  KStage* stage;
+  // structure-factor lists: [0] snapshot, [1] accumulator
+  int nk[2], nax[2], ngen[2];
+  std::vector<int32_t> klist[2];
+  int64_t sk_count;
+  int batch_refs;     // > 0 while a batch holds the lattice
+};
+
+namespace flb {
+
+char* lat_buffer(flb_lattice* h, int which) { return h->pop + (size_t)which * h->plane; }
+
+// ---------------------------------------------------------------------------
+// step launch
+template <int D, typename T>
+int launch_step_t(flb_lattice* h, const T* g, T* out, uint32_t step, hipStream_t st) {
+  const KParams<T> P = make_kparams<T>(h->p, h->rho_eq);
+  const int kern = h->p.kernel == FLB_KERNEL_AUTO ? FLB_KERNEL_ROWS : h->p.kernel;
+  if (kern == FLB_KERNEL_PLAIN) {
+    const int64_t nb = (h->n + 255) / 256;
+    k_step_plain<D, T><<<dim3((unsigned)nb), dim3(256), 0, st>>>(g, out, P, step);
+  } else {
+    const int bx = h->p.tile_x ? h->p.tile_x : 256;
+    const int ry = D == 1 ? 1 : (h->p.tile_rows ? h->p.tile_rows : 4);
+    const int64_t nrows = P.ny * P.nz;
+    const int64_t tiles_x = (P.nx + bx - 1) / bx;
+    const int64_t tiles_r = (nrows + ry - 1) / ry;
+    const int64_t G = tiles_x * tiles_r;
+    const int remap = 1;
+    dim3 grid((unsigned)G), block((unsigned)bx);
+    switch (ry) {
+      case 1: k_step_rows<D, T, 1><<<grid, block, 0, st>>>(g, out, P, step, tiles_x, nrows, remap); break;
+      case 2: k_step_rows<D, T, 2><<<grid, block, 0, st>>>(g, out, P, step, tiles_x, nrows, remap); break;
+      case 4: k_step_rows<D, T, 4><<<grid, block, 0, st>>>(g, out, P, step, tiles_x, nrows, remap); break;
+      case 8: k_step_rows<D, T, 8><<<grid, block, 0, st>>>(g, out, P, step, tiles_x, nrows, remap); break;
+      default: k_step_rows<D, T, 16><<<grid, block, 0, st>>>(g, out, P, step, tiles_x, nrows, remap); break;
+    }
+  }
+  return FLB_OK;
+}
+
+int launch_step(flb_lattice* h, const void* g, void* out, uint32_t step, hipStream_t st) {
+  if (h->s == 4) {
+    switch (h->d) {
+      case 1: return launch_step_t<1, float>(h, (const float*)g, (float*)out, step, st);
+      case 2: return launch_step_t<2, float>(h, (const float*)g, (float*)out, step, st);
+      default: return launch_step_t<3, float>(h, (const float*)g, (float*)out, step, st);
+    }
+  }
+  switch (h->d) {
+    case 1: return launch_step_t<1, double>(h, (const double*)g, (double*)out, step, st);
+    case 2: return launch_step_t<2, double>(h, (const double*)g, (double*)out, step, st);
+    default: return launch_step_t<3, double>(h, (const double*)g, (double*)out, step, st);
+  }
+}
+
+// canonical conversions
+template <typename T>
+void launch_convert_t(int d, bool to_canon, const T* src, T* dst, int64_t nx, int64_t ny, int64_t nz,
+                      hipStream_t st) {
+  const int64_t n = nx * ny * nz;
+  const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+  if (to_canon) {
+    if (d == 1) k_to_canonical<1, T><<<nb, 256, 0, st>>>(src, dst, nx, ny, nz);
+    else if (d == 2) k_to_canonical<2, T><<<nb, 256, 0, st>>>(src, dst, nx, ny, nz);
+    else k_to_canonical<3, T><<<nb, 256, 0, st>>>(src, dst, nx, ny, nz);
+  } else {
+    if (d == 1) k_from_canonical<1, T><<<nb, 256, 0, st>>>(src, dst, nx, ny, nz);
+    else if (d == 2) k_from_canonical<2, T><<<nb, 256, 0, st>>>(src, dst, nx, ny, nz);
+    else k_from_canonical<3, T><<<nb, 256, 0, st>>>(src, dst, nx, ny, nz);
+  }
+}
+
+void launch_convert(flb_lattice* h, bool to_canon, const void* src, void* dst) {
+  if (h->s == 4)
+    launch_convert_t<float>(h->d, to_canon, (const float*)src, (float*)dst, h->p.n[0], h->p.n[1], h->p.n[2], h->stream);
+  else
+    launch_convert_t<double>(h->d, to_canon, (const double*)src, (double*)dst, h->p.n[0], h->p.n[1], h->p.n[2], h->stream);
+}
+
+// lattice sums into work.red_out (device)
+template <int D, typename T>
+void launch_moments_t(flb_lattice* h, const T* g) {
+  const int64_t nb = std::min<int64_t>((h->n + 255) / 256, kRedBlocks);
+  double* part = (double*)(h->work + h->wl.red_part);
+  double* out = (double*)(h->work + h->wl.red_out);
+  k_moments_partial<D, T><<<(unsigned)nb, 256, 0, h->stream>>>(g, h->p.n[0], h->p.n[1], h->p.n[2], part);
+  k_moments_final<<<1, 64, 0, h->stream>>>(part, (int)nb, out);
+}
+
+void launch_moments(flb_lattice* h) {
+  const void* g = lat_buffer(h, h->cur);
+  if (h->s == 4) {
+    if (h->d == 1) launch_moments_t<1, float>(h, (const float*)g);
+    else if (h->d == 2) launch_moments_t<2, float>(h, (const float*)g);
+    else launch_moments_t<3, float>(h, (const float*)g);
+  } else {
+    if (h->d == 1) launch_moments_t<1, double>(h, (const double*)g);
+    else if (h->d == 2) launch_moments_t<2, double>(h, (const double*)g);
+    else launch_moments_t<3, double>(h, (const double*)g);
+  }
+}
+
+}  // namespace flb
+
+// ---------------------------------------------------------------------------
+// structure factor
+namespace {
+
+// Split a k-list into axis entries (one nonzero component, or zero, for
+// D >= 2) and general entries, reduced modulo the box.
+void classify_k(const flb_lattice* h, const int32_t* kvec, int nk, KStage* st, int* nax, int* ngen) {
+  int na = 0, ng = 0;
+  for (int j = 0; j < nk; ++j) {
+    int64_t k[3];
+    int nnz = 0, ax = -1;
+    for (int a = 0; a < 3; ++a) {
+      const int64_t L = h->p.n[a];
+      k[a] = ((int64_t)kvec[3 * j + a] % L + L) % L;
+      if (k[a] != 0) {
+        ++nnz;
+        ax = a;
+      }
+    }
+    if (h->d >= 2 && nnz <= 1) {
+      st->kinfo[2 * na] = nnz == 0 ? -1 : ax;
+      st->kinfo[2 * na + 1] = nnz == 0 ? 0 : k[ax];
+      st->slot_ax[na++] = j;
+    } else {
+      st->kv[3 * ng] = k[0];
+      st->kv[3 * ng + 1] = k[1];
+      st->kv[3 * ng + 2] = k[2];
+      st->slot_gen[ng++] = j;
+    }
+  }
+  *nax = na;
+  *ngen = ng;
+}
+
+template <int D, typename T>
+void launch_sk_t(flb_lattice* h, int set) {
+  const T* g = (const T*)flb::lat_buffer(h, h->cur);
+  const int64_t nx = h->p.n[0], ny = h->p.n[1], nz = h->p.n[2];
+  hipStream_t st = h->stream;
+  char* w = h->work;
+  double* sval = (double*)(w + h->wl.sval[set]);
+  if (h->nax[set] > 0) {
+    const int64_t nrows = ny * nz;
+    const int64_t nchunk = std::min<int64_t>(kColChunks, nrows);
+    const int64_t rpc = (nrows + nchunk - 1) / nchunk;
+    double* rowsum = (double*)(w + h->wl.rowsum);
+    double* colpart = (double*)(w + h->wl.colpart);
+    double* mx = (double*)(w + h->wl.marg);
+    double* my = mx + nx;
+    double* mz = my + ny;
+    k_row_sums<D, T><<<(unsigned)nrows, 256, 0, st>>>(g, nx, ny, nz, rowsum);
+    k_col_partial<D, T><<<dim3((unsigned)((nx + 255) / 256), (unsigned)nchunk), 256, 0, st>>>(g, nx, ny, nz, rpc, colpart);
+    const int64_t tot = nx + ny + nz;
+    k_marginals_final<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(colpart, nchunk, rowsum, nx, ny, nz, mx, my, mz);
+    k_sk_axis<<<(unsigned)h->nax[set], 256, 0, st>>>(mx, my, mz, nx, ny, nz,
+                                                     (const int64_t*)(w + h->wl.kinfo[set]),
+                                                     (const int32_t*)(w + h->wl.slot_ax[set]), sval);
+  }
+  if (h->ngen[set] > 0) {
+    const int64_t nchunk = std::min<int64_t>(kSkChunks, (h->n + 255) / 256);
+    const int64_t chunk = (h->n + nchunk - 1) / nchunk;
+    double* part = (double*)(w + h->wl.skpart);
+    k_sk_direct_partial<D, T><<<dim3((unsigned)nchunk, (unsigned)h->ngen[set]), 256, 0, st>>>(
+        g, nx, ny, nz, (const int64_t*)(w + h->wl.kv[set]), h->rho_eq, chunk, part);
+    k_sk_direct_final<<<(unsigned)((h->ngen[set] + 63) / 64), 64, 0, st>>>(
+        part, nchunk, h->ngen[set], (const int32_t*)(w + h->wl.slot_gen[set]), (double)h->n, sval);
+  }
+}
+
+void launch_sk(flb_lattice* h, int set) {
+  if (h->s == 4) {
+    if (h->d == 1) launch_sk_t<1, float>(h, set);
+    else if (h->d == 2) launch_sk_t<2, float>(h, set);
+    else launch_sk_t<3, float>(h, set);
+  } else {
+    if (h->d == 1) launch_sk_t<1, double>(h, set);
+    else if (h->d == 2) launch_sk_t<2, double>(h, set);
+    else launch_sk_t<3, double>(h, set);
+  }
+}
+
+// Upload a k-list into set `set` of the workspace; synchronises.
+int upload_k(flb_lattice* h, const int32_t* kvec, int nk, int set) {
+  KStage* st = h->stage;
+  int na = 0, ng = 0;
+  classify_k(h, kvec, nk, st, &na, &ng);
+  char* w = h->work;
+  HIP_TRY(hipMemcpyAsync(w + h->wl.kinfo[set], st->kinfo, sizeof(int64_t) * 2 * std::max(na, 1), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipMemcpyAsync(w + h->wl.slot_ax[set], st->slot_ax, sizeof(int32_t) * std::max(na, 1), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipMemcpyAsync(w + h->wl.kv[set], st->kv, sizeof(int64_t) * 3 * std::max(ng, 1), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipMemcpyAsync(w + h->wl.slot_gen[set], st->slot_gen, sizeof(int32_t) * std::max(ng, 1), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->nk[set] = nk;
+  h->nax[set] = na;
+  h->ngen[set] = ng;
+  h->klist[set].assign(kvec, kvec + 3 * nk);
+  return FLB_OK;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// exported functions
+extern "C" {
+
+int flb_version(void) { return FLB_ABI_VERSION; }
+
+const char* flb_last_error(void) { return flb::g_err.c_str(); }
+
+int flb_lattice_constants(int32_t model, double theta, double* w, double* m) {
+  if (model < 1 || model > 3) return fail(FLB_EINVAL, "model must be 1, 2 or 3");
+  const int d = model, Q = 2 * d + 1;
+  const double th = theta == 0.0 ? default_theta(d) : theta;
+  if (!(th > 0.0 && th < 1.0 / d)) return fail(FLB_EINVAL, "theta outside (0, 1/d)");
+  if (w) {
+    w[0] = 1.0 - d * th;
+    for (int i = 1; i < Q; ++i) w[i] = th / 2.0;
+  }
+  if (m) {
+    const double a = 1.0 / std::sqrt(th), b = 1.0 / std::sqrt(2.0 * th), e = 1.0 / std::sqrt(6.0 * th);
+    const double c0 = std::sqrt(d * th / (1.0 - d * th)), c1 = std::sqrt((1.0 - d * th) / (d * th));
+    std::vector<double> M((size_t)Q * Q, 0.0);
+    auto at = [&](int r, int i) -> double& { return M[(size_t)r * Q + i]; };
+    for (int i = 0; i < Q; ++i) at(0, i) = 1.0;
+    for (int ax = 0; ax < d; ++ax) {  // current moments
+      at(1 + ax, 1 + 2 * ax) = a;
+      at(1 + ax, 2 + 2 * ax) = -a;
+    }
+    int r = 1 + d;
+    if (d >= 2) {  // v_x^2 - v_y^2
+      for (int i = 1; i <= 2; ++i) at(r, i) = b;
+      for (int i = 3; i <= 4; ++i) at(r, i) = -b;
+      ++r;
+    }
+    if (d == 3) {  // v_x^2 + v_y^2 - 2 v_z^2
+      for (int i = 1; i <= 4; ++i) at(r, i) = e;
+      for (int i = 5; i <= 6; ++i) at(r, i) = -2.0 * e;
+      ++r;
+    }
+    at(r, 0) = -c0;  // trace
+    for (int i = 1; i < Q; ++i) at(r, i) = c1;
+    std::memcpy(m, M.data(), sizeof(double) * Q * Q);
+  }
+  return Q;
+}
+
+int flb_required_bytes(const flb_params* p, size_t* pop_bytes, size_t* work_bytes) {
+  int rc = check_params(p);
+  if (rc) return rc;
+  const size_t n = (size_t)(p->n[0] * p->n[1] * p->n[2]);
+  const size_t Q = 2 * p->model + 1;
+  if (pop_bytes) *pop_bytes = 2 * Q * n * (size_t)p->precision;
+  if (work_bytes) *work_bytes = work_layout(*p).total;
+  return FLB_OK;
+}
+
+int flb_create(const flb_params* p, void* d_pop, size_t pop_bytes, void* d_work, size_t work_bytes,
+               void* hip_stream, flb_lattice** out) {
+  if (!out) return fail(FLB_EINVAL, "out is NULL");
+  *out = nullptr;
+  size_t need_pop = 0, need_work = 0;
+  int rc = flb_required_bytes(p, &need_pop, &need_work);
+  if (rc) return rc;
+  if (!d_pop) return fail(FLB_EINVAL, "d_pop is NULL");
+  if (((uintptr_t)d_pop) % 256) return fail(FLB_EINVAL, "d_pop must be 256-byte aligned");
+  if (pop_bytes < need_pop) return fail(FLB_ENOMEM, "pop_bytes %zu < required %zu", pop_bytes, need_pop);
+  if (d_work && work_bytes < need_work) return fail(FLB_ENOMEM, "work_bytes %zu < required %zu", work_bytes, need_work);
+  if (d_work && ((uintptr_t)d_work) % 256) return fail(FLB_EINVAL, "d_work must be 256-byte aligned");
+  flb_lattice* h = new (std::nothrow) flb_lattice();
+  if (!h) return fail(FLB_ENOMEM, "handle allocation failed");
+  h->p = *p;
+  h->d = p->model;
+  h->Q = 2 * p->model + 1;
+  h->n = p->n[0] * p->n[1] * p->n[2];
+  h->s = (size_t)p->precision;
+  h->plane = (size_t)h->Q * h->n * h->s;
+  h->pop = (char*)d_pop;
+  h->cur = 0;
+  h->stream = (hipStream_t)hip_stream;
+  h->step = 0;
+  h->mass0 = 0;
+  h->rho_eq = 0;
+  h->sk_count = 0;
+  h->batch_refs = 0;
+  h->wl = work_layout(*p);
+  h->nk[0] = h->nk[1] = 0;
+  h->nax[0] = h->nax[1] = h->ngen[0] = h->ngen[1] = 0;
+  hipError_t e = hipGetDevice(&h->device);
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(e, "hipGetDevice");
+  }
+  if (d_work) {
+    h->work = (char*)d_work;
+    h->own_work = false;
+  } else {
+    e = hipMalloc((void**)&h->work, h->wl.total);
+    if (e != hipSuccess) {
+      delete h;
+      return fail(FLB_ENOMEM, "workspace allocation of %zu bytes failed: %s", h->wl.total, hipGetErrorString(e));
+    }
+    h->own_work = true;
+  }
+  e = hipHostMalloc((void**)&h->stage, sizeof(KStage), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    if (h->own_work) (void)hipFree(h->work);
+    delete h;
+    return hip_fail(e, "hipHostMalloc");
+  }
+  *out = h;
+  return FLB_OK;
+}
+
+int flb_destroy(flb_lattice* h) {
+  if (!h) return FLB_OK;
+  if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
+  DeviceGuard g(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  if (h->own_work) (void)hipFree(h->work);
+  (void)hipHostFree(h->stage);
+  delete h;
+  return FLB_OK;
+}
+
+int flb_set_populations(flb_lattice* h, const void* src, int src_on_device, int64_t step) {
+  if (!h || !src) return fail(FLB_EINVAL, "NULL argument");
+  if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
+  if (step < 0) return fail(FLB_EINVAL, "step must be >= 0");
+  DeviceGuard g(h->device);
+  // stage the canonical state in the spare buffer, then pull it back into
+  // storage form in the current buffer
+  const int spare = 1 - h->cur;
+  HIP_TRY(hipMemcpyAsync(lat_buffer(h, spare), src, h->plane,
+                         src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream));
+  launch_convert(h, false, lat_buffer(h, spare), lat_buffer(h, h->cur));
+  HIP_TRY(hipGetLastError());
+  launch_moments(h);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(h->stage->red, h->work + h->wl.red_out, sizeof(double) * kNV, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->mass0 = h->stage->red[0];
+  h->rho_eq = h->mass0 / (double)h->n;
+  h->step = step;
+  return FLB_OK;
+}
+
+int flb_get_populations(flb_lattice* h, void* dst, int dst_on_device) {
+  if (!h || !dst) return fail(FLB_EINVAL, "NULL argument");
+  DeviceGuard g(h->device);
+  const int spare = 1 - h->cur;
+  launch_convert(h, true, lat_buffer(h, h->cur), lat_buffer(h, spare));
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(dst, lat_buffer(h, spare), h->plane,
+                         dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return FLB_OK;
+}
+
+int flb_step(flb_lattice* h, int64_t nsteps) {
+  if (!h) return fail(FLB_EINVAL, "NULL handle");
+  if (nsteps < 0) return fail(FLB_EINVAL, "nsteps must be >= 0");
+  if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
+  DeviceGuard g(h->device);
+  for (int64_t k = 0; k < nsteps; ++k) {
+    const int nxt = 1 - h->cur;
+    launch_step(h, lat_buffer(h, h->cur), lat_buffer(h, nxt), (uint32_t)(h->step & 0xFFFFFFFF), h->stream);
+    h->cur = nxt;
+    h->step += 1;
+  }
+  HIP_TRY(hipGetLastError());
+  return FLB_OK;
+}
+
+int flb_get_step(flb_lattice* h, int64_t* step) {
+  if (!h || !step) return fail(FLB_EINVAL, "NULL argument");
+  *step = h->step;
+  return FLB_OK;
+}
+
+int flb_moments(flb_lattice* h, flb_moments_t* out) {
+  if (!h || !out) return fail(FLB_EINVAL, "NULL argument");
+  DeviceGuard g(h->device);
+  launch_moments(h);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(h->stage->red, h->work + h->wl.red_out, sizeof(double) * kNV, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  const double* r = h->stage->red;
+  std::memset(out, 0, sizeof *out);
+  out->step = h->step;
+  out->nsite = h->n;
+  out->mass = r[0];
+  out->mass0 = h->mass0;
+  out->rho_eq = h->rho_eq;
+  for (int i = 0; i < 7; ++i) out->sum_f[i] = r[1 + i];
+  for (int i = 0; i < 28; ++i) out->sum_ff[i] = r[8 + i];
+  out->sum_rho2 = r[36];
+  out->sum_rho_pos = r[37];
+  out->n_negative = (int64_t)r[38];
+  out->nonfinite = (int64_t)r[39];
+  return FLB_OK;
+}
+
+int flb_structure_factor(flb_lattice* h, const int32_t* kvec, int32_t nk, int32_t mode, double* S_out) {
+  if (!h) return fail(FLB_EINVAL, "NULL handle");
+  if (mode < 0 || mode > 3) return fail(FLB_EINVAL, "unknown mode %d", mode);
+  DeviceGuard g(h->device);
+  char* w = h->work;
+  if (mode == FLB_SK_SNAPSHOT || mode == FLB_SK_RESET) {
+    if (!kvec || nk < 1 || nk > kMaxK) return fail(FLB_EINVAL, "need 1 <= nk <= %d wave vectors", kMaxK);
+    if (mode == FLB_SK_SNAPSHOT && !S_out) return fail(FLB_EINVAL, "S_out is NULL");
+  }
+  if (mode == FLB_SK_SNAPSHOT) {
+    int rc = upload_k(h, kvec, nk, 0);
+    if (rc) return rc;
+    launch_sk(h, 0);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(h->stage->out, w + h->wl.sval[0], sizeof(double) * nk, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    std::memcpy(S_out, h->stage->out, sizeof(double) * nk);
+    return FLB_OK;
+  }
+  if (mode == FLB_SK_RESET) {
+    int rc = upload_k(h, kvec, nk, 1);
+    if (rc) return rc;
+    k_fill_zero<<<(kMaxK + 255) / 256, 256, 0, h->stream>>>((double*)(w + h->wl.skacc), kMaxK);
+    HIP_TRY(hipGetLastError());
+    h->sk_count = 0;
+    return FLB_OK;
+  }
+  if (h->nk[1] == 0) return fail(FLB_ESTATE, "structure factor accumulator has no k-list (call RESET)");
+  if (mode == FLB_SK_SAMPLE) {
+    if (kvec && (nk != h->nk[1] || std::memcmp(kvec, h->klist[1].data(), sizeof(int32_t) * 3 * nk) != 0))
+      return fail(FLB_EINVAL, "SAMPLE k-list differs from the one given at RESET");
+    launch_sk(h, 1);
+    k_sk_accumulate<<<(h->nk[1] + 255) / 256, 256, 0, h->stream>>>((const double*)(w + h->wl.sval[1]),
+                                                                   (double*)(w + h->wl.skacc), h->nk[1]);
+    HIP_TRY(hipGetLastError());
+    h->sk_count += 1;
+    return FLB_OK;
+  }
+  // READ
+  if (!S_out) return fail(FLB_EINVAL, "S_out is NULL");
+  if (h->sk_count == 0) return fail(FLB_ESTATE, "no samples accumulated");
+  HIP_TRY(hipMemcpyAsync(h->stage->out, w + h->wl.skacc, sizeof(double) * h->nk[1], hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  for (int j = 0; j < h->nk[1]; ++j) S_out[j] = h->stage->out[j] / (double)h->sk_count;
+  return FLB_OK;
+}
+
+int flb_sync(flb_lattice* h) {
+  if (!h) return fail(FLB_EINVAL, "NULL handle");
+  DeviceGuard g(h->device);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return FLB_OK;
+}
+
+int flb_noise_sample(int32_t model, int32_t precision, int32_t law, uint64_t seed, int64_t step,
+                     int64_t site0, int64_t nsite, void* d_words, void* d_vars, void* hip_stream) {
+  if (model < 1 || model > 3) return fail(FLB_EINVAL, "model must be 1, 2 or 3");
+  if (precision != 4 && precision != 8) return fail(FLB_EINVAL, "precision must be 4 or 8");
+  if (law < 0 || law > 1) return fail(FLB_EINVAL, "law must be 0 or 1");
+  if (nsite < 0 || site0 < 0 || step < 0) return fail(FLB_EINVAL, "negative size, site or step");
+  if (nsite == 0) return FLB_OK;
+  flb_params p{};
+  p.model = model;
+  p.precision = precision;
+  p.n[0] = 1;
+  p.n[1] = 1;
+  p.n[2] = 1;
+  p.omega[0] = 1.0;
+  p.seed = seed;
+  p.noise = FLB_NOISE_LOCAL;
+  p.noise_law = law;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const unsigned nb = (unsigned)((nsite + 255) / 256);
+  const uint32_t t32 = (uint32_t)(step & 0xFFFFFFFF);
+  if (precision == 4) {
+    KParams<float> P = make_kparams<float>(p, 0.0);
+    if (model == 1) k_noise_sample<1, float><<<nb, 256, 0, st>>>(P, t32, site0, nsite, (uint32_t*)d_words, (float*)d_vars);
+    else if (model == 2) k_noise_sample<2, float><<<nb, 256, 0, st>>>(P, t32, site0, nsite, (uint32_t*)d_words, (float*)d_vars);
+    else k_noise_sample<3, float><<<nb, 256, 0, st>>>(P, t32, site0, nsite, (uint32_t*)d_words, (float*)d_vars);
+  } else {
+    KParams<double> P = make_kparams<double>(p, 0.0);
+    if (model == 1) k_noise_sample<1, double><<<nb, 256, 0, st>>>(P, t32, site0, nsite, (uint32_t*)d_words, (double*)d_vars);
+    else if (model == 2) k_noise_sample<2, double><<<nb, 256, 0, st>>>(P, t32, site0, nsite, (uint32_t*)d_words, (double*)d_vars);
+    else k_noise_sample<3, double><<<nb, 256, 0, st>>>(P, t32, site0, nsite, (uint32_t*)d_words, (double*)d_vars);
+  }
+  HIP_TRY(hipGetLastError());
+  return FLB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,242 @@
+// Device-side building blocks of the fluctuating lattice Boltzmann step for
+// gfx950: the Philox noise stream, the uniform and Gaussian mappings, and the
+// per-site collision of the D1Q3 / D2Q5 / D3Q7 models.
+//
+// The collision follows eq. (collision) of Wagner & Strand (arXiv:1606.07801)
+// in moment space (Sec. II): the density rho = M^0 is conserved, every other
+// moment relaxes with its class rate omega_a = 1/tau^a towards its
+// equilibrium value 0 and receives noise of variance
+// rho_n (2 tau^a - 1)/(tau^a)^2 = rho_n omega_a (2 - omega_a)
+// (eqs. xilocal / xiglobal), with rho_n the local density clamped at zero
+// (Sec. IV) or the global mean density.  The post-collision populations are
+// formed in the equivalent increment form
+//   f_i* = f_i + sum_{a>=1} w_i m_i^a (xi^a - omega_a M^a),   i >= 1,
+//   f_0* = rho - sum_{i>=1} f_i*,
+// which uses f_i = sum_a w_i m_i^a M^a (completeness of the basis) and makes
+// each site's post-collision sum round to rho.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace flb {
+
+enum NoiseMode : int { kNoiseLocal = 0, kNoiseGlobal = 1, kNoiseOff = 2 };
+enum NoiseLaw : int { kLawGauss = 0, kLawUniform = 1 };
+
+// Everything a step kernel needs about one lattice, passed by value.
+template <typename T>
+struct KParams {
+  int64_t nx, ny, nz, n;   // box and site count
+  T a;                     // 1/sqrt(theta)           current moments
+  T b;                     // 1/sqrt(2 theta)         first traceless moment
+  T e;                     // 1/sqrt(6 theta)         second traceless moment (D3Q7)
+  T c0, c1;                // trace moment: m^s_0 = -c0, m^s_i = c1
+  T w1;                    // theta / 2, weight of every moving population
+  T om_j, om_n, om_s;      // relaxation rates per class
+  T sq_j, sq_n, sq_s;      // sqrt(omega (2 - omega)) per class, times sqrt(3) for the flat law
+  T rho_eq;                // density of the global noise mode
+  uint32_t k0, k1;         // Philox key (seed low / high word)
+  int32_t noise;           // NoiseMode
+  int32_t law;             // NoiseLaw
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11).  Ten rounds of two 32x32->64-bit
+// products on counter words 0 and 2; the high halves are mixed with words 1
+// and 3 and the key, the key advances by two Weyl increments between rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2,
+                                              uint32_t& c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+  }
+}
+
+// u = (2 (r >> 9) + 1) 2^-24: an odd multiple of 2^-24, exact in float.
+template <typename T>
+__device__ __forceinline__ T word_to_uniform(uint32_t r) {
+  return (T)((r >> 9) * 2u + 1u) * (T)5.9604644775390625e-08;  // 2^-24
+}
+
+// Box-Muller pair from two uniforms.
+__device__ __forceinline__ void box_muller(float u0, float u1, float& z0, float& z1) {
+  const float R = sqrtf(-2.0f * logf(u0));
+  float s, c;
+  sincospif(2.0f * u1, &s, &c);
+  z0 = R * c;
+  z1 = R * s;
+}
+__device__ __forceinline__ void box_muller(double u0, double u1, double& z0, double& z1) {
+  const double R = sqrt(-2.0 * log(u0));
+  double s, c;
+  sincospi(2.0 * u1, &s, &c);
+  z0 = R * c;
+  z1 = R * s;
+}
+
+// Variates for one Philox block: four unit-variance values.
+template <typename T>
+__device__ __forceinline__ void draw4(const KParams<T>& P, uint64_t site, uint32_t step,
+                                      uint32_t block, T (&z)[4]) {
+  uint32_t c0 = (uint32_t)site, c1 = (uint32_t)(site >> 32), c2 = step, c3 = block;
+  philox4x32_10(c0, c1, c2, c3, P.k0, P.k1);
+  const T u0 = word_to_uniform<T>(c0), u1 = word_to_uniform<T>(c1);
+  const T u2 = word_to_uniform<T>(c2), u3 = word_to_uniform<T>(c3);
+  if (P.law == kLawGauss) {
+    box_muller(u0, u1, z[0], z[1]);
+    box_muller(u2, u3, z[2], z[3]);
+  } else {  // flat law on (-1, 1); the sqrt(3) lives in sq_*
+    z[0] = (T)2 * u0 - (T)1;
+    z[1] = (T)2 * u1 - (T)1;
+    z[2] = (T)2 * u2 - (T)1;
+    z[3] = (T)2 * u3 - (T)1;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T noise_scale(const KParams<T>& P, T rho) {
+  const T rn = P.noise == kNoiseLocal ? (rho > (T)0 ? rho : (T)0) : P.rho_eq;
+  return sqrt(rn);
+}
+
+// ---------------------------------------------------------------------------
+// Per-site collision.  f holds the pre-collision populations of one site in
+// the velocity order 0, +x, -x, +y, -y, +z, -z and is overwritten with the
+// post-collision populations.
+template <int D, typename T>
+struct Collide;
+
+template <typename T>
+struct Collide<1, T> {
+  static constexpr int Q = 3;
+  __device__ __forceinline__ static void run(T (&f)[3], const KParams<T>& P, uint64_t site,
+                                             uint32_t step) {
+    const T rho = f[0] + f[1] + f[2];
+    const T Mj = P.a * (f[1] - f[2]);
+    const T Ms = P.c1 * (f[1] + f[2]) - P.c0 * f[0];
+    T xj = 0, xs = 0;
+    if (P.noise != kNoiseOff) {
+      T z[4];
+      draw4(P, site, step, 0u, z);
+      const T sr = noise_scale(P, rho);
+      xj = sr * P.sq_j * z[0];
+      xs = sr * P.sq_s * z[1];
+    }
+    const T dj = xj - P.om_j * Mj;
+    const T ds = xs - P.om_s * Ms;
+    const T f1 = f[1] + P.w1 * (P.a * dj + P.c1 * ds);
+    const T f2 = f[2] + P.w1 * (P.c1 * ds - P.a * dj);
+    f[1] = f1;
+    f[2] = f2;
+    f[0] = rho - (f1 + f2);
+  }
+};
+
+template <typename T>
+struct Collide<2, T> {
+  static constexpr int Q = 5;
+  __device__ __forceinline__ static void run(T (&f)[5], const KParams<T>& P, uint64_t site,
+                                             uint32_t step) {
+    const T rho = f[0] + f[1] + f[2] + f[3] + f[4];
+    const T sx = f[1] + f[2], sy = f[3] + f[4];
+    const T Mx = P.a * (f[1] - f[2]);
+    const T My = P.a * (f[3] - f[4]);
+    const T Mn = P.b * (sx - sy);
+    const T Ms = P.c1 * (sx + sy) - P.c0 * f[0];
+    T x1 = 0, x2 = 0, x3 = 0, x4 = 0;
+    if (P.noise != kNoiseOff) {
+      T z[4];
+      draw4(P, site, step, 0u, z);
+      const T sr = noise_scale(P, rho);
+      const T gj = sr * P.sq_j;
+      x1 = gj * z[0];
+      x2 = gj * z[1];
+      x3 = sr * P.sq_n * z[2];
+      x4 = sr * P.sq_s * z[3];
+    }
+    const T dx = x1 - P.om_j * Mx;
+    const T dy = x2 - P.om_j * My;
+    const T dn = x3 - P.om_n * Mn;
+    const T ds = x4 - P.om_s * Ms;
+    const T cx = P.a * dx, cy = P.a * dy;
+    const T pn = P.b * dn, ps = P.c1 * ds;
+    const T hx = pn + ps, hy = ps - pn;
+    const T f1 = f[1] + P.w1 * (hx + cx);
+    const T f2 = f[2] + P.w1 * (hx - cx);
+    const T f3 = f[3] + P.w1 * (hy + cy);
+    const T f4 = f[4] + P.w1 * (hy - cy);
+    f[1] = f1;
+    f[2] = f2;
+    f[3] = f3;
+    f[4] = f4;
+    f[0] = rho - (((f1 + f2) + f3) + f4);
+  }
+};
+
+template <typename T>
+struct Collide<3, T> {
+  static constexpr int Q = 7;
+  __device__ __forceinline__ static void run(T (&f)[7], const KParams<T>& P, uint64_t site,
+                                             uint32_t step) {
+    const T rho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6];
+    const T sx = f[1] + f[2], sy = f[3] + f[4], sz = f[5] + f[6];
+    const T Mx = P.a * (f[1] - f[2]);
+    const T My = P.a * (f[3] - f[4]);
+    const T Mz = P.a * (f[5] - f[6]);
+    const T Mn1 = P.b * (sx - sy);
+    const T Mn2 = P.e * ((sx + sy) - (T)2 * sz);
+    const T Ms = P.c1 * ((sx + sy) + sz) - P.c0 * f[0];
+    T x[6] = {0, 0, 0, 0, 0, 0};
+    if (P.noise != kNoiseOff) {
+      T z[4], zz[4];
+      draw4(P, site, step, 0u, z);
+      draw4(P, site, step, 1u, zz);
+      const T sr = noise_scale(P, rho);
+      const T gj = sr * P.sq_j, gn = sr * P.sq_n;
+      x[0] = gj * z[0];
+      x[1] = gj * z[1];
+      x[2] = gj * z[2];
+      x[3] = gn * z[3];
+      x[4] = gn * zz[0];
+      x[5] = sr * P.sq_s * zz[1];
+    }
+    const T dx = x[0] - P.om_j * Mx;
+    const T dy = x[1] - P.om_j * My;
+    const T dz = x[2] - P.om_j * Mz;
+    const T dn1 = x[3] - P.om_n * Mn1;
+    const T dn2 = x[4] - P.om_n * Mn2;
+    const T ds = x[5] - P.om_s * Ms;
+    const T cx = P.a * dx, cy = P.a * dy, cz = P.a * dz;
+    const T p1 = P.b * dn1, p2 = P.e * dn2, ps = P.c1 * ds;
+    const T hx = (p1 + p2) + ps;
+    const T hy = (p2 - p1) + ps;
+    const T hz = ps - (T)2 * p2;
+    const T f1 = f[1] + P.w1 * (hx + cx);
+    const T f2 = f[2] + P.w1 * (hx - cx);
+    const T f3 = f[3] + P.w1 * (hy + cy);
+    const T f4 = f[4] + P.w1 * (hy - cy);
+    const T f5 = f[5] + P.w1 * (hz + cz);
+    const T f6 = f[6] + P.w1 * (hz - cz);
+    f[1] = f1;
+    f[2] = f2;
+    f[3] = f3;
+    f[4] = f4;
+    f[5] = f5;
+    f[6] = f6;
+    f[0] = rho - (((((f1 + f2) + f3) + f4) + f5) + f6);
+  }
+};
+
+}  // namespace flb

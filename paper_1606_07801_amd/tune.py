@@ -1,0 +1,93 @@
+"""Launch-configuration tuner of the step kernel.
+
+The step has two kernel variants (plain: one site per thread over the flat
+site index; rows: a block covers tile_x consecutive x of tile_rows rows).
+All variants compute every site with the same arithmetic in the same order,
+so their results are bit-identical; the tuner times each candidate on the
+GPU, keeps only candidates whose state after a few steps is bit-identical
+to the plain variant's, and stores the fastest per (model, precision,
+size class) in a JSON cache next to this file (or FLB_TUNE_CACHE).
+"""
+
+import json
+import os
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.environ.get("FLB_TUNE_CACHE", os.path.join(HERE, "tuned.json"))
+
+DEFAULTS = {1: dict(kernel="rows", tile_x=256, tile_rows=1),
+            2: dict(kernel="rows", tile_x=256, tile_rows=4),
+            3: dict(kernel="rows", tile_x=256, tile_rows=4)}
+
+CANDIDATES = [("rows", tx, ry) for tx in (64, 128, 256, 512, 1024) for ry in (1, 2, 4, 8)] + [("plain", 0, 0)]
+
+
+def size_class(dims):
+    n = int(np.prod(dims))
+    return "small" if n < (1 << 16) else ("medium" if n < (1 << 22) else "large")
+
+
+def _key(d, precision, dims):
+    return f"D{d}-fp{8 * precision}-{size_class(dims)}"
+
+
+def _load():
+    try:
+        with open(CACHE) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def best_config(d, precision, dims):
+    """Kernel keyword arguments for a lattice: the cached tuning result, or
+    the defaults."""
+    ent = _load().get(_key(d, precision, dims))
+    if ent:
+        return dict(kernel=ent["kernel"], tile_x=ent["tile_x"], tile_rows=ent["tile_rows"])
+    return dict(DEFAULTS[d])
+
+
+def tune(d, precision, dims, steps=50, candidates=None, write=True, verbose=True):
+    """Time every candidate on `dims` and cache the fastest bit-identical one."""
+    import torch
+    from . import flb, inputs
+
+    w, _ = flb.constants(d)
+    f0 = inputs.poisson_counts(dims, 10.0 * w, seed=0).astype(np.float32 if precision == 4 else np.float64)
+    ref = None
+    results = []
+    for kern, tx, ry in (candidates or CANDIDATES):
+        if d == 1 and ry > 1:
+            continue
+        L = flb.Lattice(d, dims, precision=precision, omega=1.0, seed=0, kernel=kern, tile_x=tx, tile_rows=ry)
+        L.set_populations(f0)
+        L.step(3)
+        state = L.get_populations()
+        if ref is None:
+            ref = state
+        same = np.array_equal(state.view(np.uint8), ref.view(np.uint8))
+        st = L.stream
+        L.step(5)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        L.step(steps)
+        e1.record(st)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        L.close()
+        results.append(dict(kernel=kern, tile_x=tx, tile_rows=ry, ms=ms, identical=bool(same)))
+        if verbose:
+            print(f"[tune] D{d} fp{8 * precision} {dims} {kern} {tx}x{ry}: {ms * 1e3:.1f} us/step"
+                  f"{'' if same else '  (NOT bit-identical: rejected)'}", flush=True)
+    ok = [r for r in results if r["identical"]]
+    best = min(ok, key=lambda r: r["ms"])
+    if write:
+        cache = _load()
+        cache[_key(d, precision, dims)] = dict(best, dims=list(dims), when=time.strftime("%Y-%m-%d %H:%M"))
+        with open(CACHE, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+    return best, results

@@ -1,0 +1,151 @@
+"""Parity at the workloads' full sizes, in the launch configuration the
+benchmark times: sampled sites checked one by one against the oracle's
+single-step evaluation, plus properties that hold at any size."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1606_07801_amd import inputs, tune
+from tests import closed_forms as cf
+from tests.gpu_common import RTOL, gpu_lattice, report, scaled_error
+
+pytestmark = pytest.mark.gpu
+
+
+def _sample_coords(dims, n, seed=0):
+    gen = np.random.default_rng(seed)
+    pts = np.stack([gen.integers(0, L, n) for L in dims], axis=1)
+    # always include the corners and faces (periodic wrap)
+    corners = np.array(np.meshgrid(*[[0, L - 1] for L in dims], indexing="ij")).reshape(len(dims), -1).T
+    return np.concatenate([corners, pts])
+
+
+def _values_at(f, coords):
+    d = coords.shape[1]
+    idx = tuple(coords[:, a] for a in reversed(range(d)))
+    return f[(slice(None),) + idx].astype(np.float64)
+
+
+def _check_at(L, f0, p, nsample, tag):
+    """The GPU lattice L has run from the seeded state f0 (step 0) to its
+    current step T; compare sampled sites with the oracle's windowed
+    evolution of the same f0 over T steps."""
+    T = L.t
+    g = L.get_populations()
+    coords = _sample_coords(L.dims, nsample, seed=T)
+    lat = p.lattice()
+    rho_eq = float(np.asarray(f0).sum(dtype=np.float64)) / (np.asarray(f0).size // lat.Q)
+    ref = oracle.run_sites(f0, lat, p, 0, T, coords, rho_eq=rho_eq)
+    err = scaled_error(_values_at(g, coords), ref, rho_eq, lat.w)
+    return report(f"{tag} after {T} steps at {len(coords)} sites", err)
+
+
+@pytest.mark.parametrize("precision", [4, 8])
+@pytest.mark.parametrize("omega", [0.6, 1.0, 1.8])
+def test_d2q5_4096_sine_rho10(precision, omega):
+    d, dims = 2, (4096, 4096)
+    lat = oracle.make_lattice(d)
+    rho = inputs.sine_field(dims, 10.0, 0.1)
+    cfg = tune.best_config(d, precision, dims)
+    L = gpu_lattice(d, dims, precision, omega=omega, seed=0, **cfg)
+    f0 = inputs.outer(lat.w, rho).astype(np.float32 if precision == 4 else np.float64)
+    L.set_populations(f0)
+    p = oracle.Params(d=2, omega_j=omega, seed=0)
+    tag = f"D2Q5 4096^2 fp{8 * precision} w={omega}"
+    L.step(1)
+    assert _check_at(L, f0, p, 20000, tag) <= RTOL[precision]
+    L.step(99)
+    assert _check_at(L, f0, p, 8, tag) <= RTOL[precision]
+    m = L.moments()
+    assert abs(m["mass"] - m["mass0"]) <= 1e-9 * m["mass0"]
+    L.close()
+
+
+@pytest.mark.parametrize("precision", [4, 8])
+def test_d2q5_4096_low_density(precision):
+    d, dims = 2, (4096, 4096)
+    lat = oracle.make_lattice(d)
+    rho = inputs.sine_field(dims, 0.1, 0.1)
+    cfg = tune.best_config(d, precision, dims)
+    L = gpu_lattice(d, dims, precision, omega=1.0, seed=0, **cfg)
+    f0 = inputs.outer(lat.w, rho).astype(np.float32 if precision == 4 else np.float64)
+    L.set_populations(f0)
+    p = oracle.Params(d=2, omega_j=1.0, seed=0)
+    L.step(1)
+    assert _check_at(L, f0, p, 20000, f"D2Q5 4096^2 rho=0.1 fp{8 * precision}") <= RTOL[precision]
+    L.close()
+
+
+def test_d3q7_512_gaussian_fp32():
+    d, dims = 3, (512, 512, 512)
+    lat = oracle.make_lattice(d)
+    rho = inputs.gaussian_field(dims, 5.0, np.sqrt(5.0), seed=0)
+    cfg = tune.best_config(d, 4, dims)
+    L = gpu_lattice(d, dims, 4, omega=1.2, seed=0, **cfg)
+    f0 = inputs.outer(lat.w, rho).astype(np.float32)
+    del rho
+    L.set_populations(f0)
+    p = oracle.Params(d=3, omega_j=1.2, seed=0)
+    L.step(1)
+    assert _check_at(L, f0, p, 5000, "D3Q7 512^3 fp32") <= RTOL[4]
+    L.step(19)
+    assert _check_at(L, f0, p, 6, "D3Q7 512^3 fp32") <= RTOL[4]
+    m = L.moments()
+    assert abs(m["mass"] - m["mass0"]) <= 1e-6 * m["mass0"]
+    L.close()
+
+
+def test_d1q3_256_fp64_full_run():
+    # the D1Q3 workload in full: 10^4 steps, Poisson counts, every population
+    d, dims, steps = 1, (256,), 10_000
+    lat = oracle.make_lattice(d)
+    f0 = inputs.poisson_counts(dims, 10.0 * lat.w, seed=0)
+    cfg = tune.best_config(d, 8, dims)
+    L = gpu_lattice(d, dims, 8, omega=1.0, seed=0, **cfg)
+    L.set_populations(f0)
+    ks = [(k,) for k in range(1, 256)]
+    L.structure_factor(ks, mode="reset")
+    for _ in range(steps):
+        L.step(1)
+        L.structure_factor(ks, mode="sample")
+    g = L.get_populations()
+    S = L.structure_factor(None, mode="read")[:255]
+    m = L.moments()
+    L.close()
+    p = oracle.Params(d=1, omega_j=1.0, seed=0)
+    fo = oracle.run(f0, p, steps)
+    err = scaled_error(g, fo, 10.0, lat.w)
+    # 10^4 steps of rounding: the trajectories stay within the FP64 tolerance
+    assert report("D1Q3 256 fp64 10^4 steps", err) <= RTOL[8]
+    assert abs(m["mass"] - m["mass0"]) < 1e-9
+    lam = np.array([cf.ftcs_factor(lat.theta, k, dims) for k in ks])
+    sig = np.sqrt((1 + lam ** 2) / ((1 - lam ** 2) * steps))
+    z = (S / m["rho_eq"] - 1) / sig
+    print(f"[flat] D1Q3 256: max |z| {np.abs(z).max():.2f} mean z^2 {np.mean(z ** 2):.2f}")
+    assert np.abs(z).max() < 5.5 and np.mean(z ** 2) < 2.5
+
+
+@pytest.mark.parametrize("precision", [4, 8])
+@pytest.mark.parametrize("omega,k", [(1.8, 256), (1.0, 64), (0.6, 32)])
+def test_d2q5_4096_noise_off_decay_1000_steps(precision, omega, k):
+    d, dims, t = 2, (4096, 4096), 1000
+    lat = oracle.make_lattice(d)
+    rho = inputs.sine_field(dims, 10.0, 0.1)
+    cfg = tune.best_config(d, precision, dims)
+    L = gpu_lattice(d, dims, precision, omega=omega, noise="off", **cfg)
+    # sine mode of wave number k along x
+    x = np.arange(4096)
+    prof = 10.0 * (1 + 0.1 * np.sin(2 * np.pi * k * x / 4096))
+    L.set_populations(inputs.outer(lat.w, np.broadcast_to(prof, (4096, 4096)).copy()))
+    S0 = L.structure_factor([(k, 0)])[0]
+    L.step(t)
+    St = L.structure_factor([(k, 0)])[0]
+    L.close()
+    Lam = cf.lambda_f(lat.m, lat.n, np.full(lat.Q, omega))
+    g = abs(cf.density_gain(lat.w, lat.v, (k, 0), dims, Lam, t))
+    meas = np.sqrt(St / S0)
+    print(f"[decay] 4096^2 k={k} omega={omega} fp{8 * precision}: |g| {g:.10f} measured {meas:.10f}")
+    tol = 1e-8 if precision == 8 else 1e-4
+    assert abs(meas - g) <= tol * max(g, 1e-2)
+    del rho
