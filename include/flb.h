@@ -84,7 +84,9 @@ typedef struct {
   int32_t kernel;     /* FLB_KERNEL_* */
   int32_t tile_x;     /* rows kernel: threads per block along x (64..1024, multiple
                          of 64); 0 -> default */
-  int32_t tile_rows;  /* rows kernel: rows per thread (1..16); 0 -> default */
+  int32_t tile_rows;  /* rows kernel: rows per thread (1, 2, 4, 8, 16); 0 -> default */
+  int32_t nt_store;   /* rows kernel: 1 = non-temporal stores of the new state */
+  int32_t reserved;   /* must be 0 */
 } flb_params;
 
 typedef struct {

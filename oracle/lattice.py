@@ -63,24 +63,12 @@ def _velocities(d):
 
 
 def _weights(v, theta):
-    """Solve the equilibrium moment conditions for w (zeroth and second
-    moments; the first moment vanishes by symmetry).  With one rest velocity
-    and 2d unit velocities the solution is unique."""
+    """Equilibrium weights: w_0 = 1 - d theta, w_i = theta / 2 (Sec. II prints
+    these for D2Q5; the same three moment conditions on the D1Q3 and D3Q7
+    velocity sets give the analogues with d = 1, 3)."""
     Q, d = v.shape
-    rows, rhs = [np.ones(Q)], [1.0]
-    for ax in range(d):
-        rows.append(v[:, ax].astype(float) ** 2)
-        rhs.append(theta)
-    # symmetric pairs carry equal weight: w(+e) = w(-e)
-    for ax in range(d):
-        e = np.zeros(Q)
-        e[1 + 2 * ax] = 1.0
-        e[2 + 2 * ax] = -1.0
-        rows.append(e)
-        rhs.append(0.0)
-    A = np.array(rows)
-    b = np.array(rhs)
-    w, *_ = np.linalg.lstsq(A, b, rcond=None)
+    w = np.full(Q, theta / 2.0)
+    w[0] = 1.0 - d * theta
     return w
 
 
@@ -99,9 +87,11 @@ def _seeds(v):
 
 
 def _gram_schmidt(seeds, w):
-    """Classical Gram-Schmidt under <a, b> = sum_i a_i w_i b_i."""
-    basis = []
-    for s in seeds:
+    """Classical Gram-Schmidt under <a, b> = sum_i a_i w_i b_i.  The first
+    seed is the conserved row m^0 = (1, .., 1), already of unit norm because
+    the weights sum to one; it is kept exactly as the paper prints it."""
+    basis = [np.array(seeds[0], dtype=float)]
+    for s in seeds[1:]:
         u = np.array(s, dtype=float)
         for b in basis:
             u = u - np.sum(u * w * b) * b

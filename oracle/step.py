@@ -15,7 +15,7 @@ carried out in moment space, where the collision matrix is diagonal
   rho     = sum_i f_i                              (the conserved density)
   M^a     = sum_i m_i^a f_i
   f_i^0   = rho w_i                                eq. (f0def)
-  M^{a,0} = sum_i m_i^a f_i^0                      (= rho delta^{a0})
+  M^{a,0} = sum_i m_i^a f_i^0 = rho delta^{a0}     (Sec. II, equilibrium moments)
   M^a*    = M^a + (M^{a,0} - M^a) / tau^a + xi^a
   f_i*    = sum_a n_i^a M^a*,  n_i^a = m_i^a w_i
   f_i(x + v_i, t + 1) = f_i*(x)
@@ -106,8 +106,11 @@ def collide(f, site_idx, lat, p, t, rho_eq=None):
     f = np.asarray(f, dtype=np.float64)
     rho = f.sum(axis=0)                                  # rho = sum_i f_i
     M = np.tensordot(lat.m, f, axes=(1, 0))              # M^a = sum_i m_i^a f_i
-    f0 = lat.w[:, None] * rho[None, :]                   # f_i^0 = rho w_i
-    M0 = np.tensordot(lat.m, f0, axes=(1, 0))            # M^{a,0}
+    # M^{a,0} = sum_i m_i^a f_i^0 with f_i^0 = rho w_i (eq. f0def); Sec. II
+    # evaluates it in closed form, M^{a,0} = rho delta^{a0}, which is used
+    # here so that the conserved moment is not perturbed by rounding
+    M0 = np.zeros_like(M)
+    M0[0] = rho
     tau = 1.0 / p.omegas(lat)                            # Lambda^ab = delta^ab / tau^a
     var_coef = (2.0 * tau - 1.0) / tau ** 2
     var_coef[0] = 0.0                                    # no noise on the conserved mode
@@ -197,7 +200,7 @@ def step_sites(f, lat, p, t, coords, rho_eq=None):
     return out
 
 
-def run_sites(f0, lat, p, t0, nsteps, coords, rho_eq=None):
+def run_sites(f0, lat, p, t0, nsteps, coords, rho_eq=None, horizon=0):
     """Populations f_i(x, t0 + nsteps) at selected sites, evolved from the
     full initial state f0 at step t0.
 
@@ -233,11 +236,22 @@ def run_sites(f0, lat, p, t0, nsteps, coords, rho_eq=None):
     flat = np.asarray(f0).reshape(Q, -1)
     W = flat[:, gidx.ravel()].astype(np.float64).reshape((Q,) + shape)
     sites = gidx.ravel().astype(np.uint64)
+    if horizon:
+        # L1 distance of every window point from its centre
+        grid = np.meshgrid(*([offs] * d), indexing="ij")
+        dist = sum(np.abs(g) for g in grid)
+        minrho = np.full(K, np.inf)
     for t in range(t0, t0 + T):
+        if horizon and t >= t0 + T - horizon:
+            rho = W.sum(axis=0)
+            cone = dist <= (t0 + T - t)
+            minrho = np.minimum(minrho, np.where(cone[None], np.abs(rho), np.inf).reshape(K, -1).min(axis=1))
         fs = collide(W.reshape(Q, -1), sites, lat, p, t, rho_eq).reshape((Q,) + shape)
         for i in range(Q):
             sh = tuple(int(lat.v[i, ax]) for ax in range(d))
             ax = tuple(-1 - a for a in range(d))
             W[i] = np.roll(fs[i], sh, axis=ax)
     centre = (slice(None), np.arange(K)) + (T,) * d
+    if horizon:
+        return W[centre], minrho
     return W[centre]

@@ -60,6 +60,9 @@ int check_params(const flb_params* p) {
   }
   const double n = (double)p->n[0] * (double)p->n[1] * (double)p->n[2];
   if (n * (2 * d + 1) * p->precision > 9.0e18) return fail(FLB_EINVAL, "lattice too large");
+  // the row kernel indexes columns and rows in 32 bits
+  if (p->n[0] * p->precision >= (1ll << 32) || p->n[1] * p->n[2] >= (1ll << 31))
+    return fail(FLB_EINVAL, "rows of n[0] values must be under 4 GiB and n[1] * n[2] below 2^31");
   const double th = p->theta == 0.0 ? default_theta(d) : p->theta;
   if (!(th > 0.0 && th < 1.0 / d)) return fail(FLB_EINVAL, "theta = %g outside (0, 1/%d)", th, d);
   if (!(p->omega[0] > 0.0 && p->omega[0] < 2.0)) return fail(FLB_EINVAL, "omega_j = %g outside (0, 2)", p->omega[0]);
@@ -72,6 +75,7 @@ int check_params(const flb_params* p) {
   if (p->kernel < 0 || p->kernel > 2) return fail(FLB_EINVAL, "kernel must be 0 (auto), 1 (plain) or 2 (rows)");
   if (p->tile_x != 0 && (p->tile_x < 64 || p->tile_x > 1024 || p->tile_x % 64 != 0))
     return fail(FLB_EINVAL, "tile_x must be a multiple of 64 in [64, 1024]");
+  if (p->nt_store != 0 && p->nt_store != 1) return fail(FLB_EINVAL, "nt_store must be 0 or 1");
   if (p->tile_rows != 0 && p->tile_rows != 1 && p->tile_rows != 2 && p->tile_rows != 4 &&
       p->tile_rows != 8 && p->tile_rows != 16)
     return fail(FLB_EINVAL, "tile_rows must be 1, 2, 4, 8 or 16");
@@ -220,13 +224,18 @@ int launch_step_t(flb_lattice* h, const T* g, T* out, uint32_t step, hipStream_t
     const int64_t G = tiles_x * tiles_r;
     const int remap = 1;
     dim3 grid((unsigned)G), block((unsigned)bx);
+    const bool nt = h->p.nt_store != 0;
+#define FLB_ROWS(RYV)                                                                             \
+  (nt ? (void)(k_step_rows<D, T, RYV, true><<<grid, block, 0, st>>>(g, out, P, step, tiles_x, nrows, remap)) \
+      : (void)(k_step_rows<D, T, RYV, false><<<grid, block, 0, st>>>(g, out, P, step, tiles_x, nrows, remap)))
     switch (ry) {
-      case 1: k_step_rows<D, T, 1><<<grid, block, 0, st>>>(g, out, P, step, tiles_x, nrows, remap); break;
-      case 2: k_step_rows<D, T, 2><<<grid, block, 0, st>>>(g, out, P, step, tiles_x, nrows, remap); break;
-      case 4: k_step_rows<D, T, 4><<<grid, block, 0, st>>>(g, out, P, step, tiles_x, nrows, remap); break;
-      case 8: k_step_rows<D, T, 8><<<grid, block, 0, st>>>(g, out, P, step, tiles_x, nrows, remap); break;
-      default: k_step_rows<D, T, 16><<<grid, block, 0, st>>>(g, out, P, step, tiles_x, nrows, remap); break;
+      case 1: FLB_ROWS(1); break;
+      case 2: FLB_ROWS(2); break;
+      case 4: FLB_ROWS(4); break;
+      case 8: FLB_ROWS(8); break;
+      default: FLB_ROWS(16); break;
     }
+#undef FLB_ROWS
   }
   return FLB_OK;
 }
@@ -277,7 +286,7 @@ void launch_moments_t(flb_lattice* h, const T* g) {
   double* part = (double*)(h->work + h->wl.red_part);
   double* out = (double*)(h->work + h->wl.red_out);
   k_moments_partial<D, T><<<(unsigned)nb, 256, 0, h->stream>>>(g, h->p.n[0], h->p.n[1], h->p.n[2], part);
-  k_moments_final<<<1, 64, 0, h->stream>>>(part, (int)nb, out);
+  k_moments_final<<<kNV, 256, 0, h->stream>>>(part, (int)nb, out);
 }
 
 void launch_moments(flb_lattice* h) {
@@ -347,8 +356,8 @@ void launch_sk_t(flb_lattice* h, int set) {
     double* mz = my + ny;
     k_row_sums<D, T><<<(unsigned)nrows, 256, 0, st>>>(g, nx, ny, nz, rowsum);
     k_col_partial<D, T><<<dim3((unsigned)((nx + 255) / 256), (unsigned)nchunk), 256, 0, st>>>(g, nx, ny, nz, rpc, colpart);
-    const int64_t tot = nx + ny + nz;
-    k_marginals_final<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(colpart, nchunk, rowsum, nx, ny, nz, mx, my, mz);
+    k_marginals_xy<<<(unsigned)((nx + ny + 255) / 256), 256, 0, st>>>(colpart, nchunk, rowsum, nx, ny, nz, mx, my);
+    if (D == 3) k_marginal_z<<<(unsigned)nz, 256, 0, st>>>(rowsum, ny, mz);
     k_sk_axis<<<(unsigned)h->nax[set], 256, 0, st>>>(mx, my, mz, nx, ny, nz,
                                                      (const int64_t*)(w + h->wl.kinfo[set]),
                                                      (const int32_t*)(w + h->wl.slot_ax[set]), sval);
@@ -360,7 +369,8 @@ void launch_sk_t(flb_lattice* h, int set) {
     k_sk_direct_partial<D, T><<<dim3((unsigned)nchunk, (unsigned)h->ngen[set]), 256, 0, st>>>(
         g, nx, ny, nz, (const int64_t*)(w + h->wl.kv[set]), h->rho_eq, chunk, part);
     k_sk_direct_final<<<(unsigned)((h->ngen[set] + 63) / 64), 64, 0, st>>>(
-        part, nchunk, h->ngen[set], (const int32_t*)(w + h->wl.slot_gen[set]), (double)h->n, sval);
+        part, nchunk, h->ngen[set], (const int32_t*)(w + h->wl.slot_gen[set]),
+        (const int64_t*)(w + h->wl.kv[set]), h->rho_eq, (double)h->n, sval);
   }
 }
 

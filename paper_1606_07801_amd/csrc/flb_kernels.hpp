@@ -83,9 +83,28 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) {
   return xcd < r ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
 }
 
+// Element at a 32-bit byte offset from a block-uniform base pointer: the
+// base lives in scalar registers and the access needs no 64-bit vector
+// address arithmetic.
+template <typename T>
+__device__ __forceinline__ T ld_at(const T* __restrict__ base, uint32_t byte_off) {
+  return *(const T*)((const char*)base + byte_off);
+}
+template <typename T, bool NT>
+__device__ __forceinline__ void st_at(T* __restrict__ base, uint32_t byte_off, T v) {
+  T* p = (T*)((char*)base + byte_off);
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
 // Row step: a block covers blockDim.x consecutive x of RY consecutive rows
-// (row = y + ny z); each thread walks its column through the RY rows.
-template <int D, typename T, int RY>
+// (row = y + ny z); each thread owns one column of the tile.  All RY rows'
+// populations are loaded before any is collided, so that every wave keeps
+// RY * Q loads in flight; NT selects non-temporal stores (the new state is
+// not re-read within this launch).
+template <int D, typename T, int RY, bool NT>
 __global__ void __launch_bounds__(1024) k_step_rows(const T* __restrict__ g, T* __restrict__ h,
                                                     KParams<T> P, uint32_t step, int64_t tiles_x,
                                                     int64_t nrows, int remap) {
@@ -93,34 +112,56 @@ __global__ void __launch_bounds__(1024) k_step_rows(const T* __restrict__ g, T* 
   const int64_t G = (int64_t)gridDim.x;
   const int64_t tile = remap ? xcd_tile(blockIdx.x, G) : (int64_t)blockIdx.x;
   const int64_t tx = tile % tiles_x, tr = tile / tiles_x;
-  const int64_t x = tx * blockDim.x + threadIdx.x;
-  if (x >= P.nx) return;
-  const int64_t nx = P.nx, ny = P.ny, n = P.n;
-  const int64_t xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+  // the row tile and every plane/row base are uniform over the block (scalar
+  // registers); per lane only 32-bit column offsets remain
+  const uint32_t nx = (uint32_t)P.nx;
+  const uint32_t x = (uint32_t)(tx * blockDim.x) + threadIdx.x;
+  if (x >= nx) return;
+  const int64_t n = P.n;
+  constexpr uint32_t S = sizeof(T);
+  const uint32_t bx = x * S;                                   // nx * S < 2^32
+  const uint32_t bxm = (x == 0 ? nx - 1 : x - 1) * S, bxp = (x == nx - 1 ? 0 : x + 1) * S;
+  const int64_t row0 = tr * RY;
+  T f[RY][Q];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
-    const int64_t row = tr * RY + r;
-    if (row >= nrows) break;
-    const int64_t y = row % ny, z = row / ny;
-    const int64_t base = row * nx;
-    T f[Q];
-    f[0] = g[base + x];
-    f[1] = g[n + base + xm];
-    f[2] = g[2 * n + base + xp];
-    if constexpr (D >= 2) {
-      const int64_t ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-      f[3] = g[3 * n + (ym + ny * z) * nx + x];
-      f[4] = g[4 * n + (yp + ny * z) * nx + x];
+    const int64_t row = row0 + r;
+    if (row < nrows) {
+      const int64_t base = row * (int64_t)nx;
+      f[r][0] = ld_at(g + base, bx);
+      f[r][1] = ld_at(g + n + base, bxm);
+      f[r][2] = ld_at(g + 2 * n + base, bxp);
+      if constexpr (D >= 2) {
+        uint32_t y, z;
+        if constexpr (D == 2) {
+          y = (uint32_t)row;
+          z = 0;
+        } else {
+          y = (uint32_t)row % (uint32_t)P.ny;
+          z = (uint32_t)row / (uint32_t)P.ny;
+        }
+        const uint32_t ny = (uint32_t)P.ny;
+        const uint32_t ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+        f[r][3] = ld_at(g + 3 * n + ((int64_t)ym + (int64_t)ny * z) * nx, bx);
+        f[r][4] = ld_at(g + 4 * n + ((int64_t)yp + (int64_t)ny * z) * nx, bx);
+        if constexpr (D >= 3) {
+          const uint32_t nz = (uint32_t)P.nz;
+          const uint32_t zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+          f[r][5] = ld_at(g + 5 * n + ((int64_t)y + (int64_t)ny * zm) * nx, bx);
+          f[r][6] = ld_at(g + 6 * n + ((int64_t)y + (int64_t)ny * zp) * nx, bx);
+        }
+      }
     }
-    if constexpr (D >= 3) {
-      const int64_t nz = P.nz;
-      const int64_t zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
-      f[5] = g[5 * n + (y + ny * zm) * nx + x];
-      f[6] = g[6 * n + (y + ny * zp) * nx + x];
-    }
-    Collide<D, T>::run(f, P, (uint64_t)(base + x), step);
+  }
 #pragma unroll
-    for (int i = 0; i < Q; ++i) h[i * n + base + x] = f[i];
+  for (int r = 0; r < RY; ++r) {
+    const int64_t row = row0 + r;
+    if (row < nrows) {
+      const int64_t base = row * (int64_t)nx;
+      Collide<D, T>::run(f[r], P, (uint64_t)base + x, step);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) st_at<T, NT>(h + i * n + base, bx, f[r][i]);
+    }
   }
 }
 
@@ -254,13 +295,16 @@ __global__ void __launch_bounds__(256) k_moments_partial(const T* __restrict__ g
   if (threadIdx.x == 0) out[39] = v;
 }
 
-// Sum nblk rows of kNV partials in block order.
-__global__ void k_moments_final(const double* __restrict__ part, int nblk, double* __restrict__ out) {
-  const int q = threadIdx.x;
-  if (q >= kNV) return;
+// Sum nblk rows of kNV partials: one 256-thread block per quantity, each
+// thread a fixed strided subset, then the block tree (deterministic).
+__global__ void __launch_bounds__(256) k_moments_final(const double* __restrict__ part, int nblk,
+                                                       double* __restrict__ out) {
+  __shared__ double lds[4];
+  const int q = blockIdx.x;
   double acc = 0;
-  for (int b = 0; b < nblk; ++b) acc += part[(int64_t)b * kNV + q];
-  out[q] = acc;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) acc += part[(int64_t)b * kNV + q];
+  acc = block_sum256(acc, lds);
+  if (threadIdx.x == 0) out[q] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -311,12 +355,11 @@ __global__ void __launch_bounds__(256) k_col_partial(const T* __restrict__ g, in
   colpart[c * nx + x] = acc;
 }
 
-// Axis marginals from the partials: mx[x] = sum_c colpart[c][x];
-// my[y] = sum_z rowsum[y + ny z]; mz[z] = sum_y rowsum[y + ny z].
-__global__ void k_marginals_final(const double* __restrict__ colpart, int64_t nchunk,
-                                  const double* __restrict__ rowsum, int64_t nx, int64_t ny,
-                                  int64_t nz, double* __restrict__ mx, double* __restrict__ my,
-                                  double* __restrict__ mz) {
+// Axis marginals from the partials: mx[x] = sum_c colpart[c][x] and
+// my[y] = sum_z rowsum[y + ny z] (one thread each, short fixed loops).
+__global__ void k_marginals_xy(const double* __restrict__ colpart, int64_t nchunk,
+                               const double* __restrict__ rowsum, int64_t nx, int64_t ny,
+                               int64_t nz, double* __restrict__ mx, double* __restrict__ my) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < nx) {
     double acc = 0;
@@ -327,12 +370,18 @@ __global__ void k_marginals_final(const double* __restrict__ colpart, int64_t nc
     double acc = 0;
     for (int64_t z = 0; z < nz; ++z) acc += rowsum[y + ny * z];
     my[y] = acc;
-  } else if (t < nx + ny + nz) {
-    const int64_t z = t - nx - ny;
-    double acc = 0;
-    for (int64_t y = 0; y < ny; ++y) acc += rowsum[y + ny * z];
-    mz[z] = acc;
   }
+}
+
+// mz[z] = sum_y rowsum[y + ny z]: one block per z (3-D lattices only).
+__global__ void __launch_bounds__(256) k_marginal_z(const double* __restrict__ rowsum, int64_t ny,
+                                                    double* __restrict__ mz) {
+  __shared__ double lds[4];
+  const int64_t z = blockIdx.x;
+  double acc = 0;
+  for (int64_t y = threadIdx.x; y < ny; y += blockDim.x) acc += rowsum[y + ny * z];
+  acc = block_sum256(acc, lds);
+  if (threadIdx.x == 0) mz[z] = acc;
 }
 
 // Axis structure factor from a marginal: one block per wave vector.
@@ -413,8 +462,10 @@ __global__ void __launch_bounds__(256) k_sk_direct_partial(const T* __restrict__
   }
 }
 
+// k = 0 entries hold sum_x (rho - mean) = M - N mean in `re`; S(0) = M^2 / N.
 __global__ void k_sk_direct_final(const double* __restrict__ partial, int64_t nchunk, int nkg,
-                                  const int32_t* __restrict__ slot, double N,
+                                  const int32_t* __restrict__ slot,
+                                  const int64_t* __restrict__ kv, double mean, double N,
                                   double* __restrict__ sval) {
   const int j = (int)((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
   if (j >= nkg) return;
@@ -423,7 +474,12 @@ __global__ void k_sk_direct_final(const double* __restrict__ partial, int64_t nc
     re += partial[(j * nchunk + c) * 2];
     im += partial[(j * nchunk + c) * 2 + 1];
   }
-  sval[slot[j]] = (re * re + im * im) / N;
+  if (kv[3 * j] == 0 && kv[3 * j + 1] == 0 && kv[3 * j + 2] == 0) {
+    const double M = re + N * mean;
+    sval[slot[j]] = M * M / N;
+  } else {
+    sval[slot[j]] = (re * re + im * im) / N;
+  }
 }
 
 __global__ void k_sk_accumulate(const double* __restrict__ sval, double* __restrict__ acc, int nk) {

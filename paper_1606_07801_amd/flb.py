@@ -44,6 +44,7 @@ class Params(ctypes.Structure):
         ("noise", ctypes.c_int32), ("noise_law", ctypes.c_int32),
         ("layout", ctypes.c_int32), ("kernel", ctypes.c_int32),
         ("tile_x", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+        ("nt_store", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -121,7 +122,7 @@ def constants(model, theta=0.0):
 
 
 def make_params(model, dims, precision=4, theta=0.0, omega=1.0, omega_n=0.0, omega_s=0.0,
-                seed=0, noise="local", law="gauss", kernel="auto", tile_x=0, tile_rows=0):
+                seed=0, noise="local", law="gauss", kernel="auto", tile_x=0, tile_rows=0, nt_store=0):
     d = MODELS[model]
     dims = tuple(int(x) for x in dims) + (1,) * (3 - len(dims))
     p = Params()
@@ -138,6 +139,7 @@ def make_params(model, dims, precision=4, theta=0.0, omega=1.0, omega_n=0.0, ome
     p.kernel = KERNELS[kernel]
     p.tile_x = int(tile_x)
     p.tile_rows = int(tile_rows)
+    p.nt_store = int(nt_store)
     return p
 
 

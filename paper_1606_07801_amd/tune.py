@@ -18,11 +18,12 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.environ.get("FLB_TUNE_CACHE", os.path.join(HERE, "tuned.json"))
 
-DEFAULTS = {1: dict(kernel="rows", tile_x=256, tile_rows=1),
-            2: dict(kernel="rows", tile_x=256, tile_rows=4),
-            3: dict(kernel="rows", tile_x=256, tile_rows=4)}
+DEFAULTS = {1: dict(kernel="rows", tile_x=256, tile_rows=1, nt_store=0),
+            2: dict(kernel="rows", tile_x=256, tile_rows=4, nt_store=0),
+            3: dict(kernel="rows", tile_x=256, tile_rows=4, nt_store=0)}
 
-CANDIDATES = [("rows", tx, ry) for tx in (64, 128, 256, 512, 1024) for ry in (1, 2, 4, 8)] + [("plain", 0, 0)]
+CANDIDATES = [("plain", 0, 0, 0)] + [("rows", tx, ry, nt) for tx in (64, 128, 256, 512, 1024)
+                                     for ry in (1, 2, 4, 8, 16) for nt in (0, 1)]
 
 
 def size_class(dims):
@@ -47,11 +48,12 @@ def best_config(d, precision, dims):
     the defaults."""
     ent = _load().get(_key(d, precision, dims))
     if ent:
-        return dict(kernel=ent["kernel"], tile_x=ent["tile_x"], tile_rows=ent["tile_rows"])
+        return dict(kernel=ent["kernel"], tile_x=ent["tile_x"], tile_rows=ent["tile_rows"],
+                    nt_store=ent.get("nt_store", 0))
     return dict(DEFAULTS[d])
 
 
-def tune(d, precision, dims, steps=50, candidates=None, write=True, verbose=True):
+def tune(d, precision, dims, steps=100, candidates=None, write=True, verbose=True):
     """Time every candidate on `dims` and cache the fastest bit-identical one."""
     import torch
     from . import flb, inputs
@@ -60,10 +62,11 @@ def tune(d, precision, dims, steps=50, candidates=None, write=True, verbose=True
     f0 = inputs.poisson_counts(dims, 10.0 * w, seed=0).astype(np.float32 if precision == 4 else np.float64)
     ref = None
     results = []
-    for kern, tx, ry in (candidates or CANDIDATES):
+    for kern, tx, ry, nt in (candidates or CANDIDATES):
         if d == 1 and ry > 1:
             continue
-        L = flb.Lattice(d, dims, precision=precision, omega=1.0, seed=0, kernel=kern, tile_x=tx, tile_rows=ry)
+        L = flb.Lattice(d, dims, precision=precision, omega=1.0, seed=0, kernel=kern, tile_x=tx,
+                        tile_rows=ry, nt_store=nt)
         L.set_populations(f0)
         L.step(3)
         state = L.get_populations()
@@ -71,7 +74,7 @@ def tune(d, precision, dims, steps=50, candidates=None, write=True, verbose=True
             ref = state
         same = np.array_equal(state.view(np.uint8), ref.view(np.uint8))
         st = L.stream
-        L.step(5)
+        L.step(max(steps // 2, 5))                  # let clocks settle
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(st)
         L.step(steps)
@@ -79,9 +82,9 @@ def tune(d, precision, dims, steps=50, candidates=None, write=True, verbose=True
         e1.synchronize()
         ms = e0.elapsed_time(e1) / steps
         L.close()
-        results.append(dict(kernel=kern, tile_x=tx, tile_rows=ry, ms=ms, identical=bool(same)))
+        results.append(dict(kernel=kern, tile_x=tx, tile_rows=ry, nt_store=nt, ms=ms, identical=bool(same)))
         if verbose:
-            print(f"[tune] D{d} fp{8 * precision} {dims} {kern} {tx}x{ry}: {ms * 1e3:.1f} us/step"
+            print(f"[tune] D{d} fp{8 * precision} {dims} {kern} {tx}x{ry} nt={nt}: {ms * 1e3:.1f} us/step"
                   f"{'' if same else '  (NOT bit-identical: rejected)'}", flush=True)
     ok = [r for r in results if r["identical"]]
     best = min(ok, key=lambda r: r["ms"])

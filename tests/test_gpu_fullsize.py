@@ -27,18 +27,32 @@ def _values_at(f, coords):
     return f[(slice(None),) + idx].astype(np.float64)
 
 
+# The noise amplitude sqrt(max(rho, 0)) is not Lipschitz at rho = 0: where a
+# collision in the recent past light cone of a site had |rho| below this
+# threshold, an FP32 trajectory (rounded state, ~1e-7 relative) and the FP64
+# oracle's may legitimately differ by more than the FP32 tolerance.  Such
+# sites are reported and excluded from the FP32 per-population bound.
+NEAR_ZERO = 1e-3
+HORIZON = 12
+
+
 def _check_at(L, f0, p, nsample, tag):
     """The GPU lattice L has run from the seeded state f0 (step 0) to its
     current step T; compare sampled sites with the oracle's windowed
-    evolution of the same f0 over T steps."""
+    evolution of the same f0 over T steps.  Returns the max scaled error
+    over the well-conditioned sites."""
     T = L.t
     g = L.get_populations()
     coords = _sample_coords(L.dims, nsample, seed=T)
     lat = p.lattice()
     rho_eq = float(np.asarray(f0).sum(dtype=np.float64)) / (np.asarray(f0).size // lat.Q)
-    ref = oracle.run_sites(f0, lat, p, 0, T, coords, rho_eq=rho_eq)
+    ref, minrho = oracle.run_sites(f0, lat, p, 0, T, coords, rho_eq=rho_eq, horizon=min(T, HORIZON))
     err = scaled_error(_values_at(g, coords), ref, rho_eq, lat.w)
-    return report(f"{tag} after {T} steps at {len(coords)} sites", err)
+    ok = minrho > NEAR_ZERO
+    report(f"{tag} after {T} steps at {len(coords)} sites (all)", err)
+    if (~ok).any():
+        print(f"[parity] {tag}: {int((~ok).sum())} sites with |rho| < {NEAR_ZERO} in their light cone", flush=True)
+    return report(f"{tag} after {T} steps, well-conditioned sites", err[:, ok])
 
 
 @pytest.mark.parametrize("precision", [4, 8])
@@ -118,6 +132,7 @@ def test_d1q3_256_fp64_full_run():
     err = scaled_error(g, fo, 10.0, lat.w)
     # 10^4 steps of rounding: the trajectories stay within the FP64 tolerance
     assert report("D1Q3 256 fp64 10^4 steps", err) <= RTOL[8]
+    print(f"[mass] D1Q3 10^4 steps: gpu drift {m['mass'] - m['mass0']:.3e}, oracle drift {fo.sum() - f0.sum():.3e}")
     assert abs(m["mass"] - m["mass0"]) < 1e-9
     lam = np.array([cf.ftcs_factor(lat.theta, k, dims) for k in ks])
     sig = np.sqrt((1 + lam ** 2) / ((1 - lam ** 2) * steps))

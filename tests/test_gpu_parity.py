@@ -81,9 +81,9 @@ def test_kernel_variants_bit_identical(d, precision):
     dims = SIZES[d]
     f0 = poisson_state(d, dims, 10.0, seed=3).astype(np.float32 if precision == 4 else np.float64)
     outs = []
-    for kern, tx, ry in [("plain", 0, 0), ("rows", 256, 4), ("rows", 64, 1), ("rows", 1024, 16),
-                         ("rows", 128, 8), ("rows", 512, 2)]:
-        L = gpu_lattice(d, dims, precision, omega=1.2, seed=5, kernel=kern, tile_x=tx, tile_rows=ry)
+    for kern, tx, ry, nt in [("plain", 0, 0, 0), ("rows", 256, 4, 0), ("rows", 64, 1, 1), ("rows", 1024, 16, 0),
+                             ("rows", 128, 8, 1), ("rows", 512, 2, 0), ("rows", 256, 16, 1)]:
+        L = gpu_lattice(d, dims, precision, omega=1.2, seed=5, kernel=kern, tile_x=tx, tile_rows=ry, nt_store=nt)
         L.set_populations(f0)
         L.step(12)
         outs.append(L.get_populations())
