@@ -34,6 +34,9 @@ def parse():
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--requests", type=int, default=48, help="served workload: number of requests")
+    ap.add_argument("--workload", default="lattice", choices=["lattice", "d1q3", "d3q7", "batched", "served"],
+                    help="lattice: the D2Q5 4096^2 line (default); the others print their own line")
     return ap.parse_args()
 
 
@@ -75,6 +78,10 @@ def main():
     from paper_1606_07801_amd import flb, inputs, tune
 
     torch.cuda.set_device(0)
+    if args.workload != "lattice":
+        out = OTHER[args.workload](torch, flb, inputs, tune, args)
+        print(json.dumps(out), flush=True)
+        return
     n = args.size
     dims = (n, n)
     N = n * n
@@ -177,6 +184,98 @@ def cpu_baseline(flb, inputs, n, f0):
             "gpu_fp32_max_err_vs_oracle": float(err.max()),
             "gpu_fp32_max_err_well_conditioned": float(err[~flag].max()),
             "n_pops_near_rho0": int(flag.sum())}
+
+
+def _timed(torch, fn, steps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn(steps)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def bench_d1q3(torch, flb, inputs, tune, args):
+    """D1Q3, FP64, L = 256, 10^4 steps, Poisson counts at rho = 10."""
+    dims = (256,)
+    w, _ = flb.constants(1)
+    L = flb.Lattice(1, dims, precision=8, omega=1.0, seed=0, **tune.best_config(1, 8, dims))
+    L.set_populations(inputs.poisson_counts(dims, 10.0 * w, seed=0))
+    L.step(args.warmup)
+    steps = 10_000
+    ms = _timed(torch, L.step, steps)
+    m = L.moments()
+    L.close()
+    return {"workload": "D1Q3 256 fp64 rho=10 Poisson, omega=1, 10^4 steps", "ms_per_step": round(ms, 5),
+            "mlups": round(256 / (ms * 1e-3) / 1e6, 2), "mass_drift": m["mass"] - m["mass0"]}
+
+
+def bench_d3q7(torch, flb, inputs, tune, args):
+    """D3Q7, FP32 populations, 512^3, rho = 5 + sqrt(5) z, omega = 1.2, 500 steps."""
+    dims = (512, 512, 512)
+    N = 512 ** 3
+    w, _ = flb.constants(3)
+    cfg = tune.best_config(3, 4, dims)
+    L = flb.Lattice(3, dims, precision=4, omega=1.2, seed=0, **cfg)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    rho = 5.0 + np.sqrt(5.0) * torch.randn((512, 512, 512), generator=g, device="cuda", dtype=torch.float32)
+    wt = torch.tensor(w, dtype=torch.float32, device="cuda").reshape(-1, 1, 1, 1)
+    L.set_populations((wt * rho[None]).contiguous())
+    del rho
+    L.step(20)
+    steps = 500
+    ms = _timed(torch, L.step, steps)
+    m = L.moments()
+    L.close()
+    gbs = 2 * 7 * 4 * N / (ms * 1e-3) / 1e9
+    return {"workload": "D3Q7 512^3 fp32 rho=5+sqrt(5)z, omega=1.2, 500 steps", "kernel": cfg,
+            "ms_per_step": round(ms, 4), "mlups": round(N / (ms * 1e-3) / 1e6, 1),
+            "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4),
+            "mass_drift_rel": (m["mass"] - m["mass0"]) / m["mass0"]}
+
+
+def bench_batched(torch, flb, inputs, tune, args):
+    """1024 D1Q3 (L ~ U{64..4096}) + 256 D2Q5 (sides ~ U{128..1024}), FP32,
+    per-replica seed / omega / density, Poisson initial counts, 2000 steps."""
+    reps = inputs.ensemble(1024, 256, seed=0)
+    B = flb.Batch(chunk=16)
+    lats = []
+    g = torch.Generator(device="cuda").manual_seed(0)
+    sites = 0
+    for r in reps:
+        w, _ = flb.constants(r["d"])
+        L = flb.Lattice(r["d"], r["dims"], precision=4, omega=r["omega"], seed=r["seed"])
+        shape = (len(w),) + tuple(reversed(r["dims"]))
+        lam = torch.tensor(w * r["rho"], dtype=torch.float32, device="cuda").reshape((-1,) + (1,) * r["d"])
+        L.set_populations(torch.poisson(lam.expand(shape).contiguous(), generator=g))
+        B.admit(L)
+        lats.append(L)
+        sites += L.nsite
+    B.step(32)
+    steps = 2000
+    ms = _timed(torch, lambda n: (B.step(n), B.sync()), steps)
+    bytes_step = sum(2 * L.Q * 4 * L.nsite for L in lats)
+    for L in lats:
+        B.retire(L)
+        L.close()
+    B.close()
+    return {"workload": "batched: 1024 D1Q3 L~U[64,4096] + 256 D2Q5 sides~U[128,1024], fp32, 2000 steps",
+            "replicas": len(reps), "sites": sites, "ms_per_step": round(ms, 4),
+            "mlups": round(sites / (ms * 1e-3) / 1e6, 1),
+            "effective_gbs": round(bytes_step / (ms * 1e-3) / 1e9, 1)}
+
+
+def bench_served(torch, flb, inputs, tune, args):
+    from paper_1606_07801_amd import serve
+    reqs = serve.make_requests(args.requests, 200.0, seed=0)
+    S = serve.Server()
+    mk = S.run(reqs)
+    out = serve.summary(S, mk)
+    S.close()
+    out["workload"] = "served: Poisson arrivals 200/s, D1Q3/D2Q5/D3Q7, sites log-U[1e3,1e8], steps log-U[1e2,1e5], fp32"
+    return out
+
+
+OTHER = {"d1q3": bench_d1q3, "d3q7": bench_d3q7, "batched": bench_batched, "served": bench_served}
 
 
 if __name__ == "__main__":

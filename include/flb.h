@@ -67,6 +67,7 @@ enum { FLB_LAYOUT_TWO_BUFFER = 0 };
 enum { FLB_KERNEL_AUTO = 0, FLB_KERNEL_PLAIN = 1, FLB_KERNEL_ROWS = 2 };
 
 typedef struct flb_lattice flb_lattice; /* opaque */
+typedef struct flb_batch flb_batch;     /* opaque */
 
 typedef struct {
   int32_t model;      /* FLB_D1Q3 / FLB_D2Q5 / FLB_D3Q7 */
@@ -144,7 +145,8 @@ int flb_create(const flb_params* p, void* d_pop, size_t pop_bytes, void* d_work,
 int flb_set_populations(flb_lattice* h, const void* src, int src_on_device, int64_t step);
 
 /* Copy the canonical state f_i(x, t) into dst (host or device memory).
- * Synchronises the handle's stream. */
+ * Synchronises the handle's stream.  FLB_ESTATE while the lattice is a
+ * member of a batch (as for every call that reads or writes its state). */
 int flb_get_populations(flb_lattice* h, void* dst, int dst_on_device);
 
 /* Advance nsteps >= 0 time steps: eq. (LB) with eq. (collision) at every
@@ -187,6 +189,33 @@ int flb_destroy(flb_lattice* h);
 int flb_noise_sample(int32_t model, int32_t precision, int32_t law, uint64_t seed,
                      int64_t step, int64_t site0, int64_t nsite, void* d_words, void* d_vars,
                      void* hip_stream);
+
+/* ---- batched ensembles (one launch advances many lattices) ---------------
+ * A batch holds references to lattices created with flb_create (all float32
+ * or all float64, all on one device).  flb_batch_step advances every member
+ * by nsteps with results bit-identical to flb_step on each member alone: a
+ * persistent work-list kernel covers the lattices that live in global memory,
+ * and small D1Q3 lattices run whole chunks of steps inside one workgroup's
+ * LDS.  Chunks of `chunk` steps are captured once into a HIP graph and
+ * replayed.  Members may be admitted and retired between calls. */
+typedef struct {
+  int32_t chunk;        /* steps per graph (>= 1); 0 -> 16 */
+  int32_t use_graph;    /* 1 = capture chunks in a HIP graph, 0 = eager launches */
+  int32_t lds_max_bytes;/* largest D1Q3 state run LDS-resident; 0 -> 64 KiB, -1 = never */
+  int32_t workers;      /* persistent workgroups; 0 -> 4 per CU */
+  void* hip_stream;     /* stream of all batch work (NULL = null stream) */
+} flb_batch_opts;
+
+int flb_batch_create(const flb_batch_opts* opts, flb_batch** out);
+/* Add a lattice; it must not be stepped on its own while it is a member. */
+int flb_batch_admit(flb_batch* b, flb_lattice* h);
+/* Remove a lattice (its state stays valid and can be read or stepped alone). */
+int flb_batch_retire(flb_batch* b, flb_lattice* h);
+/* Advance every member by nsteps.  Asynchronous on the batch stream. */
+int flb_batch_step(flb_batch* b, int64_t nsteps);
+int flb_batch_size(flb_batch* b, int32_t* n);
+int flb_batch_sync(flb_batch* b);
+int flb_batch_destroy(flb_batch* b);
 
 #ifdef __cplusplus
 }

@@ -14,8 +14,11 @@
 #include "../../include/flb.h"
 #include "flb_internal.hpp"
 #include "flb_kernels.hpp"
+#include "flb_stats.hpp"
 
 using namespace flb;
+
+static_assert(kNV == kNVals, "lattice-sum count");
 
 // ---------------------------------------------------------------------------
 // errors
@@ -121,21 +124,7 @@ template KParams<double> make_kparams<double>(const flb_params&, double);
 
 // ---------------------------------------------------------------------------
 // workspace layout
-namespace {
-
-constexpr int kRedBlocks = 1024;
-constexpr int kMaxK = 1024;
-constexpr int kSkChunks = 256;
-constexpr int kColChunks = 64;
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-struct WorkLayout {
-  size_t red_part, red_out, rowsum, colpart, marg, skpart, total;
-  // two k-list sets: [0] snapshot, [1] accumulator
-  size_t kinfo[2], kv[2], slot_ax[2], slot_gen[2], sval[2];
-  size_t skacc;
-};
+namespace flb {
 
 WorkLayout work_layout(const flb_params& p) {
   WorkLayout L{};
@@ -167,40 +156,7 @@ WorkLayout work_layout(const flb_params& p) {
   return L;
 }
 
-// staging for k-lists and results (pinned host memory)
-struct KStage {
-  int64_t kinfo[2 * kMaxK];
-  int64_t kv[3 * kMaxK];
-  int32_t slot_ax[kMaxK];
-  int32_t slot_gen[kMaxK];
-  double out[kMaxK];
-  double red[kNV];
-};
-
-}  // namespace
-
-struct flb_lattice {
-  flb_params p;
-  int d, Q;
-  int64_t n;
-  size_t s;           // bytes per real
-  size_t plane;       // bytes of one buffer (Q * n * s)
-  char* pop;          // two buffers
-  int cur;            // buffer holding the current state
-  char* work;
-  bool own_work;
-  WorkLayout wl;
-  hipStream_t stream;
-  int device;
-  int64_t step;
-  double mass0, rho_eq;
-  KStage* stage;
-  // structure-factor lists: [0] snapshot, [1] accumulator
-  int nk[2], nax[2], ngen[2];
-  std::vector<int32_t> klist[2];
-  int64_t sk_count;
-  int batch_refs;     // > 0 while a batch holds the lattice
-};
+}  // namespace flb
 
 namespace flb {
 
@@ -564,6 +520,7 @@ int flb_set_populations(flb_lattice* h, const void* src, int src_on_device, int6
 
 int flb_get_populations(flb_lattice* h, void* dst, int dst_on_device) {
   if (!h || !dst) return fail(FLB_EINVAL, "NULL argument");
+  if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
   DeviceGuard g(h->device);
   const int spare = 1 - h->cur;
   launch_convert(h, true, lat_buffer(h, h->cur), lat_buffer(h, spare));
@@ -597,6 +554,7 @@ int flb_get_step(flb_lattice* h, int64_t* step) {
 
 int flb_moments(flb_lattice* h, flb_moments_t* out) {
   if (!h || !out) return fail(FLB_EINVAL, "NULL argument");
+  if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
   DeviceGuard g(h->device);
   launch_moments(h);
   HIP_TRY(hipGetLastError());
@@ -620,6 +578,7 @@ int flb_moments(flb_lattice* h, flb_moments_t* out) {
 
 int flb_structure_factor(flb_lattice* h, const int32_t* kvec, int32_t nk, int32_t mode, double* S_out) {
   if (!h) return fail(FLB_EINVAL, "NULL handle");
+  if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
   if (mode < 0 || mode > 3) return fail(FLB_EINVAL, "unknown mode %d", mode);
   DeviceGuard g(h->device);
   char* w = h->work;

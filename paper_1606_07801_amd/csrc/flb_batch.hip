@@ -1,0 +1,439 @@
+// Batched ensembles: many lattices of uneven size and dimension advanced by
+// one persistent work-list launch per step (lattices in HBM) and one
+// LDS-resident launch per chunk of steps (small D1Q3 lattices), the chunk
+// captured once into a HIP graph and replayed.  Every member's arithmetic,
+// noise keys and storage order are those of flb_step on the member alone,
+// so results are bit-identical to stepping each lattice by itself.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "flb_internal.hpp"
+#include "flb_kernels.hpp"
+
+using namespace flb;
+
+namespace flb {
+
+// One member as the device sees it.  step0 / cur0 describe the state at the
+// start of the current chunk and are advanced on the device at its end, so a
+// captured chunk can be replayed.
+template <typename T>
+struct BatchRep {
+  char* pop;        // the member's two population buffers
+  int64_t plane;    // bytes of one buffer
+  KParams<T> P;
+  int64_t tiles_x;  // tiles of kBatchTX columns
+  int64_t nrows;    // ny * nz
+  int64_t step0;    // steps completed at the start of the chunk
+  int32_t cur0;     // buffer holding the state at the start of the chunk
+  int32_t pad;
+};
+
+constexpr int kBatchTX = 256;  // tile width of the work-list kernel
+constexpr int kBatchRY = 2;    // rows per tile
+
+// Persistent work list: item w is tile item_tile[w] of member item_rep[w].
+template <int D, typename T>
+__global__ void __launch_bounds__(kBatchTX) k_batch_rows(const BatchRep<T>* __restrict__ reps,
+                                                         const int32_t* __restrict__ item_rep,
+                                                         const int32_t* __restrict__ item_tile,
+                                                         int nitems, int k) {
+  for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+    const int r = __builtin_amdgcn_readfirstlane(item_rep[w]);
+    const int64_t tile = __builtin_amdgcn_readfirstlane(item_tile[w]);
+    const BatchRep<T>& R = reps[r];
+    const KParams<T> P = R.P;
+    const uint32_t step = (uint32_t)((uint64_t)(R.step0 + k) & 0xFFFFFFFFull);
+    const int par = (R.cur0 + k) & 1;
+    const T* g = (const T*)(R.pop + par * R.plane);
+    T* h = (T*)(R.pop + (par ^ 1) * R.plane);
+    rows_tile<D, T, kBatchRY, true>(g, h, P, step, tile % R.tiles_x, tile / R.tiles_x, R.nrows);
+  }
+}
+
+// A whole D1Q3 lattice in one workgroup's LDS for c steps.  The LDS holds
+// the canonical pre-collision state; a step reads each site, collides it in
+// registers, and after a barrier pushes the populations to their
+// destinations.  The last step stores the post-collision populations at
+// their collision sites in the member's other-parity buffer, the storage form
+// flb_step leaves.
+template <typename T, int SPT>
+__global__ void __launch_bounds__(256) k_batch_lds_d1(const BatchRep<T>* __restrict__ reps,
+                                                      const int32_t* __restrict__ lds_rep, int c) {
+  extern __shared__ unsigned char smem_raw[];
+  T* s0 = (T*)smem_raw;
+  const int r = __builtin_amdgcn_readfirstlane(lds_rep[blockIdx.x]);
+  const BatchRep<T>& R = reps[r];
+  const KParams<T> P = R.P;
+  const int L = (int)P.nx;
+  T* s1 = s0 + L;
+  T* s2 = s1 + L;
+  const int tid = threadIdx.x;
+  const T* g = (const T*)(R.pop + R.cur0 * R.plane);
+  for (int x = tid; x < L; x += 256) {  // f_i(x) = g_i(x - v_i)
+    s0[x] = g[x];
+    s1[x] = g[L + (x == 0 ? L - 1 : x - 1)];
+    s2[x] = g[2 * L + (x == L - 1 ? 0 : x + 1)];
+  }
+  __syncthreads();
+  T* out = (T*)(R.pop + ((R.cur0 + c) & 1) * R.plane);
+  for (int k = 0; k < c; ++k) {
+    const uint32_t step = (uint32_t)((uint64_t)(R.step0 + k) & 0xFFFFFFFFull);
+    T f[SPT][3];
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+      const int x = tid + 256 * j;
+      if (x < L) {
+        f[j][0] = s0[x];
+        f[j][1] = s1[x];
+        f[j][2] = s2[x];
+        Collide<1, T>::run(f[j], P, (uint64_t)x, step);
+      }
+    }
+    __syncthreads();
+    if (k + 1 < c) {
+#pragma unroll
+      for (int j = 0; j < SPT; ++j) {
+        const int x = tid + 256 * j;
+        if (x < L) {
+          s0[x] = f[j][0];
+          s1[x == L - 1 ? 0 : x + 1] = f[j][1];
+          s2[x == 0 ? L - 1 : x - 1] = f[j][2];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < SPT; ++j) {
+        const int x = tid + 256 * j;
+        if (x < L) {
+          out[x] = f[j][0];
+          out[L + x] = f[j][1];
+          out[2 * L + x] = f[j][2];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ void k_batch_advance(BatchRep<T>* __restrict__ reps, int n, int c) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    reps[i].step0 += c;
+    reps[i].cur0 = (reps[i].cur0 + c) & 1;
+  }
+}
+
+}  // namespace flb
+
+struct flb_batch {
+  flb_batch_opts o;
+  hipStream_t stream;
+  bool own_stream;
+  int device;
+  int ncu;
+  std::vector<flb_lattice*> members;
+  int precision;  // 0 until the first member
+  bool dirty;
+  // device table: reps, then the item lists and the LDS member list
+  char* d_table;
+  size_t table_cap;
+  size_t off_items[4][2];  // per dimension class 1..3: item_rep, item_tile
+  int nitems[4];
+  size_t off_lds;
+  int nlds, lds_spt;
+  size_t lds_bytes;
+  int nreps;
+  hipGraphExec_t exec;
+  int exec_chunk;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                  \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr);  \
+  } while (0)
+
+struct DevGuard {
+  int prev = -1;
+  explicit DevGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DevGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+int spt_for(int64_t L) {
+  const int64_t need = (L + 255) / 256;
+  return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 16;
+}
+
+void drop_graph(flb_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  b->exec = nullptr;
+  b->exec_chunk = 0;
+}
+
+// Rebuild the device table from the members' host state (stream idle).
+template <typename T>
+int rebuild_t(flb_batch* b) {
+  const int n = (int)b->members.size();
+  std::vector<BatchRep<T>> reps(n);
+  std::vector<int32_t> items[4][2];
+  std::vector<int32_t> lds;
+  int64_t lmax = 0;
+  const int64_t lds_max = b->o.lds_max_bytes < 0 ? -1 : (b->o.lds_max_bytes ? b->o.lds_max_bytes : 65536);
+  for (int i = 0; i < n; ++i) {
+    flb_lattice* h = b->members[i];
+    BatchRep<T>& R = reps[i];
+    std::memset(&R, 0, sizeof R);
+    R.pop = h->pop;
+    R.plane = (int64_t)h->plane;
+    R.P = make_kparams<T>(h->p, h->rho_eq);
+    R.tiles_x = (h->p.n[0] + kBatchTX - 1) / kBatchTX;
+    R.nrows = h->p.n[1] * h->p.n[2];
+    R.step0 = h->step;
+    R.cur0 = h->cur;
+    const int64_t state_bytes = (int64_t)h->Q * h->n * (int64_t)sizeof(T);
+    if (h->d == 1 && lds_max > 0 && state_bytes <= lds_max && h->n <= 256 * 16) {
+      lds.push_back(i);
+      lmax = std::max<int64_t>(lmax, h->n);
+      continue;
+    }
+    const int64_t ntile = R.tiles_x * ((R.nrows + kBatchRY - 1) / kBatchRY);
+    if (ntile >= (1ll << 31)) return fail(FLB_EINVAL, "member %d has too many tiles", i);
+    for (int64_t t = 0; t < ntile; ++t) {
+      items[h->d][0].push_back(i);
+      items[h->d][1].push_back((int32_t)t);
+    }
+  }
+  size_t o = align256(sizeof(BatchRep<T>) * std::max(n, 1));
+  for (int d = 1; d <= 3; ++d) {
+    b->nitems[d] = (int)items[d][0].size();
+    b->off_items[d][0] = o;
+    o += align256(sizeof(int32_t) * std::max<size_t>(items[d][0].size(), 1));
+    b->off_items[d][1] = o;
+    o += align256(sizeof(int32_t) * std::max<size_t>(items[d][1].size(), 1));
+  }
+  b->off_lds = o;
+  o += align256(sizeof(int32_t) * std::max<size_t>(lds.size(), 1));
+  if (o > b->table_cap) {
+    if (b->d_table) HIP_TRY(hipFree(b->d_table));
+    b->d_table = nullptr;
+    hipError_t e = hipMalloc((void**)&b->d_table, o);
+    if (e != hipSuccess) return fail(FLB_ENOMEM, "batch table allocation of %zu bytes failed", o);
+    b->table_cap = o;
+  }
+  HIP_TRY(hipMemcpy(b->d_table, reps.data(), sizeof(BatchRep<T>) * n, hipMemcpyHostToDevice));
+  for (int d = 1; d <= 3; ++d)
+    for (int k = 0; k < 2; ++k)
+      if (!items[d][k].empty())
+        HIP_TRY(hipMemcpy(b->d_table + b->off_items[d][k], items[d][k].data(),
+                          sizeof(int32_t) * items[d][k].size(), hipMemcpyHostToDevice));
+  if (!lds.empty())
+    HIP_TRY(hipMemcpy(b->d_table + b->off_lds, lds.data(), sizeof(int32_t) * lds.size(), hipMemcpyHostToDevice));
+  b->nlds = (int)lds.size();
+  b->lds_spt = spt_for(lmax);
+  b->lds_bytes = (size_t)(3 * lmax * (int64_t)sizeof(T));
+  b->nreps = n;
+  b->dirty = false;
+  drop_graph(b);
+  return FLB_OK;
+}
+
+template <typename T>
+void enqueue_chunk_t(flb_batch* b, int c) {
+  const BatchRep<T>* reps = (const BatchRep<T>*)b->d_table;
+  hipStream_t st = b->stream;
+  if (b->nlds > 0) {
+    const int32_t* lr = (const int32_t*)(b->d_table + b->off_lds);
+    const dim3 grid(b->nlds), block(256);
+    switch (b->lds_spt) {
+      case 1: k_batch_lds_d1<T, 1><<<grid, block, b->lds_bytes, st>>>(reps, lr, c); break;
+      case 2: k_batch_lds_d1<T, 2><<<grid, block, b->lds_bytes, st>>>(reps, lr, c); break;
+      case 4: k_batch_lds_d1<T, 4><<<grid, block, b->lds_bytes, st>>>(reps, lr, c); break;
+      case 8: k_batch_lds_d1<T, 8><<<grid, block, b->lds_bytes, st>>>(reps, lr, c); break;
+      default: k_batch_lds_d1<T, 16><<<grid, block, b->lds_bytes, st>>>(reps, lr, c); break;
+    }
+  }
+  const int workers_per_cu = b->o.workers > 0 ? 0 : 8;
+  for (int k = 0; k < c; ++k) {
+    for (int d = 1; d <= 3; ++d) {
+      const int ni = b->nitems[d];
+      if (ni == 0) continue;
+      const int grid = std::max(1, std::min(ni, b->o.workers > 0 ? b->o.workers : workers_per_cu * b->ncu));
+      const int32_t* ir = (const int32_t*)(b->d_table + b->off_items[d][0]);
+      const int32_t* it = (const int32_t*)(b->d_table + b->off_items[d][1]);
+      if (d == 1) k_batch_rows<1, T><<<grid, kBatchTX, 0, st>>>(reps, ir, it, ni, k);
+      else if (d == 2) k_batch_rows<2, T><<<grid, kBatchTX, 0, st>>>(reps, ir, it, ni, k);
+      else k_batch_rows<3, T><<<grid, kBatchTX, 0, st>>>(reps, ir, it, ni, k);
+    }
+  }
+  k_batch_advance<T><<<(b->nreps + 255) / 256, 256, 0, st>>>((BatchRep<T>*)b->d_table, b->nreps, c);
+}
+
+void enqueue_chunk(flb_batch* b, int c) {
+  if (b->precision == 4) enqueue_chunk_t<float>(b, c);
+  else enqueue_chunk_t<double>(b, c);
+}
+
+int capture(flb_batch* b, int c) {
+  drop_graph(b);
+  hipGraph_t graph = nullptr;
+  HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  enqueue_chunk(b, c);
+  hipError_t e = hipStreamEndCapture(b->stream, &graph);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    b->exec = nullptr;
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  b->exec_chunk = c;
+  return FLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int flb_batch_create(const flb_batch_opts* opts, flb_batch** out) {
+  if (!out) return fail(FLB_EINVAL, "out is NULL");
+  *out = nullptr;
+  flb_batch_opts o{};
+  if (opts) o = *opts;
+  if (o.chunk < 0 || o.chunk > 4096) return fail(FLB_EINVAL, "chunk must be in [0, 4096]");
+  if (o.workers < 0) return fail(FLB_EINVAL, "workers must be >= 0");
+  if (o.lds_max_bytes > 65536) return fail(FLB_EINVAL, "lds_max_bytes must be <= 65536");
+  if (o.chunk == 0) o.chunk = 16;
+  flb_batch* b = new (std::nothrow) flb_batch();
+  if (!b) return fail(FLB_ENOMEM, "batch allocation failed");
+  b->o = o;
+  b->precision = 0;
+  b->dirty = true;
+  b->d_table = nullptr;
+  b->table_cap = 0;
+  b->exec = nullptr;
+  b->exec_chunk = 0;
+  b->nlds = 0;
+  b->nreps = 0;
+  for (int d = 0; d < 4; ++d) b->nitems[d] = 0;
+  hipError_t e = hipGetDevice(&b->device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, b->device);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e, "device query");
+  }
+  if (o.hip_stream) {
+    b->stream = (hipStream_t)o.hip_stream;
+    b->own_stream = false;
+  } else {
+    // a stream of our own (the null stream cannot be captured); default priority
+    e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete b;
+      return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    b->own_stream = true;
+  }
+  *out = b;
+  return FLB_OK;
+}
+
+int flb_batch_admit(flb_batch* b, flb_lattice* h) {
+  if (!b || !h) return fail(FLB_EINVAL, "NULL argument");
+  if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is already in a batch");
+  if (h->device != b->device) return fail(FLB_EINVAL, "lattice and batch are on different devices");
+  if (b->precision && (int)h->s != b->precision)
+    return fail(FLB_EINVAL, "batch holds precision %d, lattice has %d", b->precision, (int)h->s);
+  DevGuard g(b->device);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  b->members.push_back(h);
+  b->precision = (int)h->s;
+  h->batch_refs += 1;
+  b->dirty = true;
+  return FLB_OK;
+}
+
+int flb_batch_retire(flb_batch* b, flb_lattice* h) {
+  if (!b || !h) return fail(FLB_EINVAL, "NULL argument");
+  auto it = std::find(b->members.begin(), b->members.end(), h);
+  if (it == b->members.end()) return fail(FLB_EINVAL, "lattice is not a member of this batch");
+  DevGuard g(b->device);
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  b->members.erase(it);
+  h->batch_refs -= 1;
+  if (b->members.empty()) b->precision = 0;
+  b->dirty = true;
+  return FLB_OK;
+}
+
+int flb_batch_step(flb_batch* b, int64_t nsteps) {
+  if (!b) return fail(FLB_EINVAL, "NULL batch");
+  if (nsteps < 0) return fail(FLB_EINVAL, "nsteps must be >= 0");
+  if (b->members.empty() || nsteps == 0) return FLB_OK;
+  DevGuard g(b->device);
+  if (b->dirty) {
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    const int rc = b->precision == 4 ? rebuild_t<float>(b) : rebuild_t<double>(b);
+    if (rc) return rc;
+  }
+  const int c = b->o.chunk;
+  const int64_t chunks = nsteps / c;
+  const int rem = (int)(nsteps % c);
+  if (chunks > 0) {
+    if (b->o.use_graph) {
+      if (!b->exec || b->exec_chunk != c) {
+        const int rc = capture(b, c);
+        if (rc) return rc;
+      }
+      for (int64_t i = 0; i < chunks; ++i) HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    } else {
+      for (int64_t i = 0; i < chunks; ++i) enqueue_chunk(b, c);
+    }
+  }
+  if (rem) enqueue_chunk(b, rem);
+  HIP_TRY(hipGetLastError());
+  for (flb_lattice* h : b->members) {
+    h->step += nsteps;
+    h->cur = (int)((h->cur + nsteps) & 1);
+  }
+  return FLB_OK;
+}
+
+int flb_batch_size(flb_batch* b, int32_t* n) {
+  if (!b || !n) return fail(FLB_EINVAL, "NULL argument");
+  *n = (int32_t)b->members.size();
+  return FLB_OK;
+}
+
+int flb_batch_sync(flb_batch* b) {
+  if (!b) return fail(FLB_EINVAL, "NULL batch");
+  DevGuard g(b->device);
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  return FLB_OK;
+}
+
+int flb_batch_destroy(flb_batch* b) {
+  if (!b) return FLB_OK;
+  DevGuard g(b->device);
+  (void)hipStreamSynchronize(b->stream);
+  for (flb_lattice* h : b->members) h->batch_refs -= 1;
+  drop_graph(b);
+  if (b->d_table) (void)hipFree(b->d_table);
+  if (b->own_stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+  return FLB_OK;
+}
+
+}  // extern "C"

@@ -13,7 +13,8 @@
 //   f_i* = f_i + sum_{a>=1} w_i m_i^a (xi^a - omega_a M^a),   i >= 1,
 //   f_0* = rho - sum_{i>=1} f_i*,
 // which uses f_i = sum_a w_i m_i^a M^a (completeness of the basis) and makes
-// each site's post-collision sum round to rho.
+// each site's post-collision sum round to rho (the density and the residual
+// are formed in double for float populations).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -111,24 +112,35 @@ __device__ __forceinline__ void draw4(const KParams<T>& P, uint64_t site, uint32
   }
 }
 
-// Site density sum_i f_i in index order.  Float populations are summed in
-// double and rounded once, so that the density (and with it the clamp at
-// zero of the noise amplitude) is the correctly rounded sum of the stored
-// values; near rho = 0 the amplitude sqrt(rho) is not Lipschitz and a float
-// rounding of the sum would otherwise be amplified.
-template <int Q>
-__device__ __forceinline__ double density_sum(const double (&f)[Q]) {
-  double r = f[0];
-#pragma unroll
-  for (int i = 1; i < Q; ++i) r += f[i];
-  return r;
-}
-template <int Q>
-__device__ __forceinline__ float density_sum(const float (&f)[Q]) {
+// Site density sum_i f_i in index order, in double.  For float populations
+// this is the correctly rounded sum of the stored values, so that the clamp
+// at zero of the noise amplitude (where sqrt(rho) is not Lipschitz) is
+// decided on the exact density.
+template <typename T, int Q>
+__device__ __forceinline__ double density_sum(const T (&f)[Q]) {
   double r = (double)f[0];
 #pragma unroll
   for (int i = 1; i < Q; ++i) r += (double)f[i];
-  return (float)r;
+  return r;
+}
+
+// Rest population after the collision, f_0* = rho - sum_{i>=1} f_i*.  For
+// float populations the residual is formed in double and rounded once, so
+// the stored populations of a site sum to rho within half an ulp of f_0*
+// without a systematic bias (exact mass conservation up to that rounding).
+template <int N>
+__device__ __forceinline__ float rest_of(double rho, const float (&fi)[N]) {
+  double s = (double)fi[0];
+#pragma unroll
+  for (int i = 1; i < N; ++i) s += (double)fi[i];
+  return (float)(rho - s);
+}
+template <int N>
+__device__ __forceinline__ double rest_of(double rho, const double (&fi)[N]) {
+  double s = fi[0];
+#pragma unroll
+  for (int i = 1; i < N; ++i) s += fi[i];
+  return rho - s;
 }
 
 __device__ __forceinline__ double noise_scale(const KParams<double>& P, double rho) {
@@ -152,7 +164,8 @@ struct Collide<1, T> {
   static constexpr int Q = 3;
   __device__ __forceinline__ static void run(T (&f)[3], const KParams<T>& P, uint64_t site,
                                              uint32_t step) {
-    const T rho = density_sum<3>(f);
+    const double rho_d = density_sum(f);
+    const T rho = (T)rho_d;
     const T Mj = P.a * (f[1] - f[2]);
     const T Ms = P.c1 * (f[1] + f[2]) - P.c0 * f[0];
     T xj = 0, xs = 0;
@@ -169,7 +182,8 @@ struct Collide<1, T> {
     const T f2 = f[2] + P.w1 * (P.c1 * ds - P.a * dj);
     f[1] = f1;
     f[2] = f2;
-    f[0] = rho - (f1 + f2);
+    const T mv[2] = {f1, f2};
+    f[0] = rest_of(rho_d, mv);
   }
 };
 
@@ -178,7 +192,8 @@ struct Collide<2, T> {
   static constexpr int Q = 5;
   __device__ __forceinline__ static void run(T (&f)[5], const KParams<T>& P, uint64_t site,
                                              uint32_t step) {
-    const T rho = density_sum<5>(f);
+    const double rho_d = density_sum(f);
+    const T rho = (T)rho_d;
     const T sx = f[1] + f[2], sy = f[3] + f[4];
     const T Mx = P.a * (f[1] - f[2]);
     const T My = P.a * (f[3] - f[4]);
@@ -210,7 +225,8 @@ struct Collide<2, T> {
     f[2] = f2;
     f[3] = f3;
     f[4] = f4;
-    f[0] = rho - (((f1 + f2) + f3) + f4);
+    const T mv[4] = {f1, f2, f3, f4};
+    f[0] = rest_of(rho_d, mv);
   }
 };
 
@@ -219,7 +235,8 @@ struct Collide<3, T> {
   static constexpr int Q = 7;
   __device__ __forceinline__ static void run(T (&f)[7], const KParams<T>& P, uint64_t site,
                                              uint32_t step) {
-    const T rho = density_sum<7>(f);
+    const double rho_d = density_sum(f);
+    const T rho = (T)rho_d;
     const T sx = f[1] + f[2], sy = f[3] + f[4], sz = f[5] + f[6];
     const T Mx = P.a * (f[1] - f[2]);
     const T My = P.a * (f[3] - f[4]);
@@ -264,7 +281,8 @@ struct Collide<3, T> {
     f[4] = f4;
     f[5] = f5;
     f[6] = f6;
-    f[0] = rho - (((((f1 + f2) + f3) + f4) + f5) + f6);
+    const T mv[6] = {f1, f2, f3, f4, f5, f6};
+    f[0] = rest_of(rho_d, mv);
   }
 };
 

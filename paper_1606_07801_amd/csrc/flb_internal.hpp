@@ -1,10 +1,67 @@
 // Declarations shared by the translation units of the library.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <string>
+#include <vector>
 
 #include "../../include/flb.h"
 #include "flb_device.hpp"
+
+namespace flb {
+
+constexpr int kRedBlocks = 1024;  // blocks of the lattice-sum reduction
+constexpr int kMaxK = 1024;       // wave vectors per structure-factor list
+constexpr int kSkChunks = 256;    // site chunks of the direct structure factor
+constexpr int kColChunks = 64;    // row chunks of the column marginals
+constexpr int kNVals = 40;        // lattice sums (see k_moments_partial)
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Byte offsets of the workspace regions.
+struct WorkLayout {
+  size_t red_part, red_out, rowsum, colpart, marg, skpart, total;
+  // two k-list sets: [0] snapshot, [1] accumulator
+  size_t kinfo[2], kv[2], slot_ax[2], slot_gen[2], sval[2];
+  size_t skacc;
+};
+WorkLayout work_layout(const flb_params& p);
+
+// Pinned host staging of one lattice.
+struct KStage {
+  int64_t kinfo[2 * kMaxK];
+  int64_t kv[3 * kMaxK];
+  int32_t slot_ax[kMaxK];
+  int32_t slot_gen[kMaxK];
+  double out[kMaxK];
+  double red[kNVals];
+};
+
+}  // namespace flb
+
+struct flb_lattice {
+  flb_params p;
+  int d, Q;
+  int64_t n;
+  size_t s;           // bytes per real
+  size_t plane;       // bytes of one buffer (Q * n * s)
+  char* pop;          // two buffers
+  int cur;            // buffer holding the current state
+  char* work;
+  bool own_work;
+  flb::WorkLayout wl;
+  hipStream_t stream;
+  int device;
+  int64_t step;
+  double mass0, rho_eq;
+  flb::KStage* stage;
+  // structure-factor lists: [0] snapshot, [1] accumulator
+  int nk[2], nax[2], ngen[2];
+  std::vector<int32_t> klist[2];
+  int64_t sk_count;
+  int batch_refs;     // > 0 while a batch holds the lattice
+};
 
 namespace flb {
 

@@ -1,0 +1,296 @@
+// Statistics kernels of one lattice (lattice sums, axis marginals and the
+// density structure factor), in deterministic FP64 reductions: fixed grid,
+// fixed shuffle trees, partials combined in block order.  Included by the
+// single translation unit that launches them.
+#pragma once
+
+#include "flb_kernels.hpp"
+
+namespace flb {
+
+// ---------------------------------------------------------------------------
+// Deterministic block reductions (fixed shuffle tree, then waves in order).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over a 256-thread block; the result is valid in thread 0.
+__device__ __forceinline__ double block_sum256(double v, double* lds4) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds4[wave] = v;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0) r = ((lds4[0] + lds4[1]) + lds4[2]) + lds4[3];
+  return r;
+}
+
+// Lattice sums: [0] mass, [1..7] sum f_i, [8..35] sum f_i f_j (i <= j),
+// [36] sum rho^2, [37] sum max(rho, 0), [38] #rho < 0, [39] #non-finite.
+constexpr int kNV = 40;
+
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_moments_partial(const T* __restrict__ g, int64_t nx,
+                                                         int64_t ny, int64_t nz,
+                                                         double* __restrict__ part) {
+  constexpr int Q = 2 * D + 1;
+  constexpr int NFF = Q * (Q + 1) / 2;
+  __shared__ double lds[4];
+  const int64_t n = nx * ny * nz;
+  double sf[Q], sff[NFF];
+  double mass = 0, r2 = 0, rpos = 0, nneg = 0, nonfin = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) sf[i] = 0;
+#pragma unroll
+  for (int i = 0; i < NFF; ++i) sff[i] = 0;
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t x = s % nx, rest = s / nx, y = rest % ny, z = rest / ny;
+    const Nbr b = neighbours(x, y, z, nx, ny, nz);
+    T fv[Q];
+    gather<D, T>(g, n, b, fv);
+    double f[Q];
+    double rho = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      f[i] = (double)fv[i];
+      rho += f[i];
+      sf[i] += f[i];
+      nonfin += isfinite(f[i]) ? 0.0 : 1.0;
+    }
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+#pragma unroll
+      for (int j = i; j < Q; ++j) sff[k++] += f[i] * f[j];
+    mass += rho;
+    r2 += rho * rho;
+    rpos += rho > 0 ? rho : 0.0;
+    nneg += rho < 0 ? 1.0 : 0.0;
+  }
+  double* out = part + (int64_t)blockIdx.x * kNV;
+  double v;
+  v = block_sum256(mass, lds);
+  if (threadIdx.x == 0) out[0] = v;
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    v = block_sum256(i < Q ? sf[i < Q ? i : 0] : 0.0, lds);
+    if (threadIdx.x == 0) out[1 + i] = i < Q ? v : 0.0;
+  }
+  // sum_ff packed for the lattice's Q, padded with zeros to 28
+#pragma unroll
+  for (int i = 0; i < 28; ++i) {
+    v = block_sum256(i < NFF ? sff[i < NFF ? i : 0] : 0.0, lds);
+    if (threadIdx.x == 0) out[8 + i] = i < NFF ? v : 0.0;
+  }
+  v = block_sum256(r2, lds);
+  if (threadIdx.x == 0) out[36] = v;
+  v = block_sum256(rpos, lds);
+  if (threadIdx.x == 0) out[37] = v;
+  v = block_sum256(nneg, lds);
+  if (threadIdx.x == 0) out[38] = v;
+  v = block_sum256(nonfin, lds);
+  if (threadIdx.x == 0) out[39] = v;
+}
+
+// Sum nblk rows of kNV partials: one 256-thread block per quantity, each
+// thread a fixed strided subset, then the block tree (deterministic).
+__global__ void __launch_bounds__(256) k_moments_final(const double* __restrict__ part, int nblk,
+                                                       double* __restrict__ out) {
+  __shared__ double lds[4];
+  const int q = blockIdx.x;
+  double acc = 0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) acc += part[(int64_t)b * kNV + q];
+  acc = block_sum256(acc, lds);
+  if (threadIdx.x == 0) out[q] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Density of a site in FP64 (canonical gather, populations in index order).
+template <int D, typename T>
+__device__ __forceinline__ double site_density(const T* __restrict__ g, int64_t n, int64_t x,
+                                               int64_t y, int64_t z, int64_t nx, int64_t ny,
+                                               int64_t nz) {
+  const Nbr b = neighbours(x, y, z, nx, ny, nz);
+  T fv[2 * D + 1];
+  gather<D, T>(g, n, b, fv);
+  double rho = 0;
+#pragma unroll
+  for (int i = 0; i < 2 * D + 1; ++i) rho += (double)fv[i];
+  return rho;
+}
+
+// Row sums: rowsum[row] = sum_x rho(x, row), one block per row.
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_row_sums(const T* __restrict__ g, int64_t nx, int64_t ny,
+                                                  int64_t nz, double* __restrict__ rowsum) {
+  __shared__ double lds[4];
+  const int64_t n = nx * ny * nz;
+  const int64_t row = blockIdx.x;
+  const int64_t y = row % ny, z = row / ny;
+  double acc = 0;
+  for (int64_t x = threadIdx.x; x < nx; x += blockDim.x)
+    acc += site_density<D, T>(g, n, x, y, z, nx, ny, nz);
+  const double v = block_sum256(acc, lds);
+  if (threadIdx.x == 0) rowsum[row] = v;
+}
+
+// Column partials: colpart[c][x] = sum over the rows of chunk c of rho(x, row).
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_col_partial(const T* __restrict__ g, int64_t nx, int64_t ny,
+                                                     int64_t nz, int64_t rows_per_chunk,
+                                                     double* __restrict__ colpart) {
+  const int64_t n = nx * ny * nz;
+  const int64_t nrows = ny * nz;
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (x >= nx) return;
+  const int64_t r0 = c * rows_per_chunk;
+  const int64_t r1 = r0 + rows_per_chunk < nrows ? r0 + rows_per_chunk : nrows;
+  double acc = 0;
+  for (int64_t row = r0; row < r1; ++row)
+    acc += site_density<D, T>(g, n, x, row % ny, row / ny, nx, ny, nz);
+  colpart[c * nx + x] = acc;
+}
+
+// Axis marginals from the partials: mx[x] = sum_c colpart[c][x] and
+// my[y] = sum_z rowsum[y + ny z] (one thread each, short fixed loops).
+__global__ void k_marginals_xy(const double* __restrict__ colpart, int64_t nchunk,
+                               const double* __restrict__ rowsum, int64_t nx, int64_t ny,
+                               int64_t nz, double* __restrict__ mx, double* __restrict__ my) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nx) {
+    double acc = 0;
+    for (int64_t c = 0; c < nchunk; ++c) acc += colpart[c * nx + t];
+    mx[t] = acc;
+  } else if (t < nx + ny) {
+    const int64_t y = t - nx;
+    double acc = 0;
+    for (int64_t z = 0; z < nz; ++z) acc += rowsum[y + ny * z];
+    my[y] = acc;
+  }
+}
+
+// mz[z] = sum_y rowsum[y + ny z]: one block per z (3-D lattices only).
+__global__ void __launch_bounds__(256) k_marginal_z(const double* __restrict__ rowsum, int64_t ny,
+                                                    double* __restrict__ mz) {
+  __shared__ double lds[4];
+  const int64_t z = blockIdx.x;
+  double acc = 0;
+  for (int64_t y = threadIdx.x; y < ny; y += blockDim.x) acc += rowsum[y + ny * z];
+  acc = block_sum256(acc, lds);
+  if (threadIdx.x == 0) mz[z] = acc;
+}
+
+// Axis structure factor from a marginal: one block per wave vector.
+// kinfo[j] = (axis, k mod L_axis); axis < 0 marks a k = 0 entry.
+// S = |sum_x (m(x) - mean) e^{-2 pi i k x / L}|^2 / N; k = 0 gives M^2 / N.
+__global__ void __launch_bounds__(256) k_sk_axis(const double* __restrict__ mx,
+                                                 const double* __restrict__ my,
+                                                 const double* __restrict__ mz, int64_t nx,
+                                                 int64_t ny, int64_t nz,
+                                                 const int64_t* __restrict__ kinfo,
+                                                 const int32_t* __restrict__ slot,
+                                                 double* __restrict__ sval) {
+  __shared__ double lds[4];
+  const int j = blockIdx.x;
+  const int64_t axis = kinfo[2 * j], k = kinfo[2 * j + 1];
+  const double N = (double)(nx * ny * nz);
+  const double* m = axis == 1 ? my : (axis == 2 ? mz : mx);
+  const int64_t L = axis == 1 ? ny : (axis == 2 ? nz : nx);
+  // mass from the chosen marginal
+  double tot = 0;
+  for (int64_t x = threadIdx.x; x < L; x += blockDim.x) tot += m[x];
+  tot = block_sum256(tot, lds);
+  __shared__ double mean_s;
+  if (threadIdx.x == 0) mean_s = tot / (double)L;
+  __syncthreads();
+  const double mean = mean_s;
+  if (axis < 0) {
+    if (threadIdx.x == 0) sval[slot[j]] = tot * tot / N;
+    return;
+  }
+  double re = 0, im = 0;
+  for (int64_t x = threadIdx.x; x < L; x += blockDim.x) {
+    const int64_t p = (k * x) % L;  // integer phase
+    double s, c;
+    sincospi(2.0 * (double)p / (double)L, &s, &c);
+    const double v = m[x] - mean;
+    re += v * c;
+    im -= v * s;
+  }
+  re = block_sum256(re, lds);
+  __syncthreads();
+  im = block_sum256(im, lds);
+  if (threadIdx.x == 0) sval[slot[j]] = (re * re + im * im) / N;
+}
+
+// General wave vectors: direct sum over sites.  Block (c, j) sums the sites
+// of chunk c for wave vector j; partial[(j * nchunk + c) * 2 + {0, 1}].
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_sk_direct_partial(const T* __restrict__ g, int64_t nx,
+                                                           int64_t ny, int64_t nz,
+                                                           const int64_t* __restrict__ kv,
+                                                           double mean, int64_t chunk,
+                                                           double* __restrict__ partial) {
+  __shared__ double lds[4];
+  const int64_t n = nx * ny * nz;
+  const int64_t c = blockIdx.x, j = blockIdx.y, nchunk = gridDim.x;
+  const int64_t kx = kv[3 * j], ky = kv[3 * j + 1], kz = kv[3 * j + 2];
+  const int64_t s0 = c * chunk, s1 = s0 + chunk < n ? s0 + chunk : n;
+  double re = 0, im = 0;
+  for (int64_t s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
+    const int64_t x = s % nx, rest = s / nx, y = rest % ny, z = rest / ny;
+    const double v = site_density<D, T>(g, n, x, y, z, nx, ny, nz) - mean;
+    // phase / (2 pi) = sum_a ((k_a x_a) mod L_a) / L_a, reduced mod 1
+    double ph = (double)((kx * x) % nx) / (double)nx + (double)((ky * y) % ny) / (double)ny +
+                (double)((kz * z) % nz) / (double)nz;
+    ph -= floor(ph);
+    double sn, cs;
+    sincospi(2.0 * ph, &sn, &cs);
+    re += v * cs;
+    im -= v * sn;
+  }
+  re = block_sum256(re, lds);
+  __syncthreads();
+  im = block_sum256(im, lds);
+  if (threadIdx.x == 0) {
+    partial[(j * nchunk + c) * 2] = re;
+    partial[(j * nchunk + c) * 2 + 1] = im;
+  }
+}
+
+// k = 0 entries hold sum_x (rho - mean) = M - N mean in `re`; S(0) = M^2 / N.
+__global__ void k_sk_direct_final(const double* __restrict__ partial, int64_t nchunk, int nkg,
+                                  const int32_t* __restrict__ slot,
+                                  const int64_t* __restrict__ kv, double mean, double N,
+                                  double* __restrict__ sval) {
+  const int j = (int)((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  if (j >= nkg) return;
+  double re = 0, im = 0;
+  for (int64_t c = 0; c < nchunk; ++c) {
+    re += partial[(j * nchunk + c) * 2];
+    im += partial[(j * nchunk + c) * 2 + 1];
+  }
+  if (kv[3 * j] == 0 && kv[3 * j + 1] == 0 && kv[3 * j + 2] == 0) {
+    const double M = re + N * mean;
+    sval[slot[j]] = M * M / N;
+  } else {
+    sval[slot[j]] = (re * re + im * im) / N;
+  }
+}
+
+__global__ void k_sk_accumulate(const double* __restrict__ sval, double* __restrict__ acc, int nk) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < nk) acc[j] += sval[j];
+}
+
+__global__ void k_fill_zero(double* __restrict__ p, int64_t n) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) p[j] = 0.0;
+}
+
+}  // namespace flb

@@ -1,0 +1,225 @@
+"""Continuous-batching server for fluctuating lattice Boltzmann solves.
+
+Requests (model, box, steps, relaxation rate, mean density, seed) arrive
+over time.  The server keeps one batch (flb_batch_*) of resident lattices:
+a request is admitted as soon as its device memory (populations + workspace,
+from flb_required_bytes) fits in the HBM budget, joins the running batch at
+the next tick, and is retired when it has done its steps; its final
+statistics are read and its memory released, which lets queued requests in.
+Every tick advances all active lattices by the same number of steps in one
+batched launch, so work of requests that arrived at different times
+overlaps on the device.  Because the batch is bit-identical to stepping
+each lattice alone, a request's result does not depend on what it was
+batched with.
+
+    python -m paper_1606_07801_amd.serve --requests 48 --rate 200
+"""
+
+import argparse
+import json
+import math
+import time
+from collections import deque
+
+import numpy as np
+
+from . import flb, inputs
+
+
+class Request:
+    __slots__ = ("id", "arrival", "d", "dims", "steps", "omega", "rho", "seed", "precision",
+                 "lat", "bytes", "start", "done", "remaining", "result", "error", "keep_state")
+
+    def __init__(self, rid, arrival, d, dims, steps, omega, rho, seed, precision=4, keep_state=False):
+        self.id, self.arrival, self.d, self.dims = rid, float(arrival), int(d), tuple(int(x) for x in dims)
+        self.steps, self.omega, self.rho, self.seed = int(steps), float(omega), float(rho), int(seed)
+        self.precision = precision
+        self.lat = None
+        self.bytes = 0
+        self.start = self.done = None
+        self.remaining = self.steps
+        self.result = None
+        self.error = None
+        self.keep_state = keep_state
+
+    @property
+    def sites(self):
+        return int(np.prod(self.dims))
+
+    @classmethod
+    def from_dict(cls, r, precision=4, keep_state=False):
+        return cls(r["id"], r["arrival"], r["d"], r["dims"], r["steps"], r["omega"], r["rho"],
+                   r["seed"], precision, keep_state)
+
+
+def request_bytes(req):
+    p = flb.make_params(req.d, req.dims, precision=req.precision, omega=req.omega, seed=req.seed)
+    pop, work = flb.required_bytes(p)
+    return pop + work + 512
+
+
+def initial_state(torch, req, device):
+    """Uniform equilibrium f_i = w_i rho (the library's weights), built on
+    the device."""
+    w, _ = flb.constants(req.d)
+    dt = torch.float32 if req.precision == 4 else torch.float64
+    wt = torch.tensor(w, dtype=dt, device=device).reshape((-1,) + (1,) * req.d)
+    shape = tuple(reversed(req.dims))
+    return (wt * req.rho).expand((len(w),) + shape).contiguous()
+
+
+def start_request(torch, req, device):
+    L = flb.Lattice(req.d, req.dims, precision=req.precision, omega=req.omega, seed=req.seed,
+                    noise="local")
+    f0 = initial_state(torch, req, device)
+    L.set_populations(f0)
+    del f0
+    req.lat = L
+
+
+def finish_request(req):
+    L = req.lat
+    m = L.moments()
+    res = {"id": req.id, "steps": L.t, "mass": m["mass"], "mass0": m["mass0"],
+           "var_rho": m["sum_rho2"] / m["nsite"] - (m["mass"] / m["nsite"]) ** 2,
+           "n_negative": m["n_negative"], "nonfinite": m["nonfinite"]}
+    if req.keep_state:
+        res["state"] = L.get_populations()
+    L.close()
+    req.lat = None
+    req.result = res
+
+
+class Server:
+    """Admission by HBM budget, continuous batching by ticks."""
+
+    def __init__(self, budget_bytes=None, tick_steps=64, chunk=16, use_graph=True, device=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        if budget_bytes is None:
+            free, _ = torch.cuda.mem_get_info(self.device)
+            budget_bytes = int(0.8 * free)
+        self.budget = int(budget_bytes)
+        self.used = 0
+        self.tick_steps = int(tick_steps)
+        self.batch = flb.Batch(chunk=chunk, use_graph=use_graph)
+        self.queue = deque()
+        self.active = []
+        self.finished = []
+        self.rejected = []
+        self.ticks = 0
+        self.site_updates = 0
+
+    def submit(self, req):
+        req.bytes = request_bytes(req)
+        if req.bytes > self.budget:
+            req.error = f"needs {req.bytes} bytes, budget is {self.budget}"
+            self.rejected.append(req)
+            return False
+        self.queue.append(req)
+        return True
+
+    def _admit(self, now):
+        while self.queue and self.queue[0].bytes <= self.budget - self.used:
+            req = self.queue.popleft()
+            start_request(self.torch, req, self.device)
+            self.used += req.bytes
+            req.start = now
+            if req.remaining == 0:
+                self._retire(req, now)
+                continue
+            self.batch.admit(req.lat)
+            self.active.append(req)
+
+    def _retire(self, req, now):
+        if req in self.active:
+            self.active.remove(req)
+            self.batch.retire(req.lat)
+        finish_request(req)
+        self.used -= req.bytes
+        req.done = now
+        self.finished.append(req)
+
+    def tick(self, now):
+        """One scheduling step: admit what fits, advance the batch, retire."""
+        self._admit(now)
+        if not self.active:
+            return 0
+        n = min(self.tick_steps, min(r.remaining for r in self.active))
+        self.batch.step(n)
+        self.batch.sync()
+        self.ticks += 1
+        t = time.perf_counter()
+        for r in list(self.active):
+            r.remaining -= n
+            self.site_updates += r.sites * n
+            if r.remaining == 0:
+                self._retire(r, t)
+        return n
+
+    def run(self, requests, clock=time.perf_counter):
+        """Serve `requests` (sorted by arrival time, seconds from now) until
+        all are finished.  Arrivals are released by the wall clock."""
+        t0 = clock()
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        for r in pending:
+            r.arrival += t0
+        while pending or self.queue or self.active:
+            now = clock()
+            while pending and pending[0].arrival <= now:
+                self.submit(pending.popleft())
+            if not self.queue and not self.active:
+                if pending:
+                    time.sleep(max(0.0, min(pending[0].arrival - clock(), 0.01)))
+                continue
+            self.tick(now)
+        return clock() - t0
+
+    def close(self):
+        self.batch.close()
+
+
+def summary(server, makespan):
+    lat = np.array([r.done - r.arrival for r in server.finished])
+    ups = server.site_updates
+    return {
+        "requests": len(server.finished), "rejected": len(server.rejected),
+        "makespan_s": round(makespan, 3),
+        "p50_latency_s": round(float(np.percentile(lat, 50)), 4) if len(lat) else None,
+        "p99_latency_s": round(float(np.percentile(lat, 99)), 4) if len(lat) else None,
+        "mlups": round(ups / makespan / 1e6, 1) if makespan > 0 else None,
+        "ticks": server.ticks,
+    }
+
+
+def make_requests(n, rate, seed=0, sites=(1e3, 1e8), steps=(1e2, 1e5), precision=4):
+    return [Request.from_dict(r, precision) for r in
+            inputs.request_stream(n, rate, seed=seed, sites=sites, steps=steps)]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=48)
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--max-sites", type=float, default=1e8)
+    ap.add_argument("--max-steps", type=float, default=1e5)
+    ap.add_argument("--budget-gb", type=float, default=0.0)
+    ap.add_argument("--tick", type=int, default=64)
+    args = ap.parse_args()
+    import torch
+    torch.cuda.set_device(0)
+    reqs = make_requests(args.requests, args.rate, args.seed, sites=(1e3, args.max_sites),
+                         steps=(1e2, args.max_steps))
+    S = Server(budget_bytes=int(args.budget_gb * 2 ** 30) if args.budget_gb else None, tick_steps=args.tick)
+    mk = S.run(reqs)
+    out = summary(S, mk)
+    out.update({"rate_per_s": args.rate, "work_site_updates": S.site_updates,
+                "budget_gb": round(S.budget / 2 ** 30, 1)})
+    S.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,174 @@
+"""Batched ensembles: each member's state after a batched run must be
+bit-identical to the same lattice stepped alone (and therefore within the
+oracle tolerance, checked for a few members); graph replay must equal eager
+launches; members can be admitted and retired between calls."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1606_07801_amd import flb, inputs
+from tests.gpu_common import RTOL, report, scaled_error
+
+pytestmark = pytest.mark.gpu
+
+
+def _member(spec, precision):
+    d, dims, omega, rho, seed = spec
+    lat = oracle.make_lattice(d)
+    f0 = inputs.poisson_counts(dims, rho * lat.w, seed=seed).astype(np.float32 if precision == 4 else np.float64)
+    return f0, dict(omega=omega, seed=seed, noise="local")
+
+
+def _specs():
+    gen = np.random.default_rng(5)
+    out = []
+    # small D1Q3 (LDS-resident), a large D1Q3 (global), D2Q5 and D3Q7 of uneven sizes
+    for L in (64, 100, 1000, 4096, 3333):
+        out.append((1, (L,), float(gen.uniform(0.5, 1.9)), float(gen.uniform(0.1, 50)), int(gen.integers(1, 1 << 40))))
+    out.append((1, (20000,), 1.3, 7.0, 17))
+    for dims in ((128, 130), (300, 17), (257, 64)):
+        out.append((2, dims, float(gen.uniform(0.5, 1.9)), float(gen.uniform(0.1, 50)), int(gen.integers(1, 1 << 40))))
+    out.append((3, (40, 33, 17), 1.1, 5.0, 99))
+    return out
+
+
+def _alone(specs, precision, nsteps, t0):
+    res = []
+    for spec in specs:
+        f0, kw = _member(spec, precision)
+        L = flb.Lattice(spec[0], spec[1], precision=precision, **kw)
+        L.set_populations(f0, step=t0)
+        L.step(nsteps)
+        res.append(L.get_populations())
+        L.close()
+    return res
+
+
+@pytest.mark.parametrize("precision", [4, 8])
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_bit_identical_to_alone(precision, use_graph):
+    specs = _specs()
+    nsteps, t0 = 37, 5           # 2 chunks of 16 + a remainder of 5
+    ref = _alone(specs, precision, nsteps, t0)
+    B = flb.Batch(chunk=16, use_graph=use_graph)
+    lats = []
+    for spec in specs:
+        f0, kw = _member(spec, precision)
+        L = flb.Lattice(spec[0], spec[1], precision=precision, **kw)
+        L.set_populations(f0, step=t0)
+        B.admit(L)
+        lats.append(L)
+    assert len(B) == len(specs)
+    B.step(nsteps)
+    B.sync()
+    for L, r, spec in zip(lats, ref, specs):
+        B.retire(L)
+        assert L.t == t0 + nsteps
+        g = L.get_populations()
+        assert np.array_equal(g.view(np.uint8), r.view(np.uint8)), spec
+        L.close()
+    B.close()
+
+
+def test_batch_members_match_oracle():
+    specs = [s for s in _specs() if s[0] == 1 and s[1][0] <= 1000] + [s for s in _specs() if s[0] == 3]
+    B = flb.Batch(chunk=8)
+    lats, f0s = [], []
+    for spec in specs:
+        f0, kw = _member(spec, 8)
+        L = flb.Lattice(spec[0], spec[1], precision=8, **kw)
+        L.set_populations(f0)
+        B.admit(L)
+        lats.append(L)
+        f0s.append(f0)
+    B.step(20)
+    for L, f0, spec in zip(lats, f0s, specs):
+        B.retire(L)
+        g = L.get_populations()
+        p = oracle.Params(d=spec[0], omega_j=spec[2], seed=spec[4])
+        fo = oracle.run(f0, p, 20)
+        assert report(f"batch member D{spec[0]} {spec[1]}", scaled_error(g, fo, spec[3], p.lattice().w)) <= RTOL[8]
+        L.close()
+    B.close()
+
+
+def test_admit_retire_between_calls():
+    # a member that joins late or leaves early ends where it would alone
+    specs = _specs()[:6] + _specs()[6:8]
+    ref_a = _alone(specs, 4, 30, 0)
+    B = flb.Batch(chunk=4)
+    lats = []
+    for i, spec in enumerate(specs):
+        f0, kw = _member(spec, 4)
+        L = flb.Lattice(spec[0], spec[1], precision=4, **kw)
+        L.set_populations(f0)
+        lats.append(L)
+    first, late = lats[: len(lats) // 2], lats[len(lats) // 2:]
+    for L in first:
+        B.admit(L)
+    B.step(10)
+    for L in late:       # late members step 10 alone first
+        L.step(10)
+        L.sync()
+        B.admit(L)
+    B.step(13)
+    B.retire(first[0])   # one member leaves, finishes alone
+    first[0].step(7)
+    B.step(7)
+    for L in lats:
+        if L is not first[0]:
+            B.retire(L)
+    for L, r in zip(lats, ref_a):
+        assert L.t == 30
+        assert np.array_equal(L.get_populations(), r)
+        L.close()
+    B.close()
+
+
+def test_batch_errors():
+    B = flb.Batch()
+    a = flb.Lattice(1, (64,), precision=4)
+    b = flb.Lattice(1, (64,), precision=8)
+    a.set_populations(np.ones((3, 64), dtype=np.float32))
+    B.admit(a)
+    with pytest.raises(flb.FlbError) as e:
+        B.admit(b)                    # mixed precision
+    assert e.value.code == flb.FLB_EINVAL
+    with pytest.raises(flb.FlbError) as e:
+        a.step(1)                     # a member is stepped by its batch only
+    assert e.value.code == flb.FLB_ESTATE
+    with pytest.raises(flb.FlbError):
+        B.admit(a)                    # already a member
+    with pytest.raises(flb.FlbError):
+        B.retire(b)                   # not a member
+    B.retire(a)
+    a.step(1)
+    a.close()
+    b.close()
+    B.close()
+
+
+def test_lds_path_equals_global_path():
+    # the same small D1Q3 lattices with the LDS path disabled
+    specs = [s for s in _specs() if s[0] == 1 and s[1][0] <= 4096]
+    outs = []
+    for lds in (0, -1):
+        B = flb.Batch(chunk=16, lds_max_bytes=lds)
+        lats = []
+        for spec in specs:
+            f0, kw = _member(spec, 4)
+            L = flb.Lattice(1, spec[1], precision=4, **kw)
+            L.set_populations(f0)
+            B.admit(L)
+            lats.append(L)
+        B.step(40)
+        res = []
+        for L in lats:
+            B.retire(L)
+            res.append(L.get_populations())
+            L.close()
+        B.close()
+        outs.append(res)
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)

@@ -72,7 +72,12 @@ def test_d2q5_4096_sine_rho10(precision, omega):
     L.step(99)
     assert _check_at(L, f0, p, 8, tag) <= RTOL[precision]
     m = L.moments()
-    assert abs(m["mass"] - m["mass0"]) <= 1e-9 * m["mass0"]
+    # exact in real arithmetic; per site and step the stored populations sum
+    # to rho within half an ulp of f_0*, an unbiased error: a random walk
+    eps = np.finfo(np.float32 if precision == 4 else np.float64).eps
+    bound = 4 * eps * 10.0 * np.sqrt(m["nsite"] * 100.0)
+    print(f"[mass] {tag}: drift {m['mass'] - m['mass0']:.3e} (bound {bound:.3e})")
+    assert abs(m["mass"] - m["mass0"]) <= bound
     L.close()
 
 
@@ -106,7 +111,9 @@ def test_d3q7_512_gaussian_fp32():
     L.step(19)
     assert _check_at(L, f0, p, 6, "D3Q7 512^3 fp32") <= RTOL[4]
     m = L.moments()
-    assert abs(m["mass"] - m["mass0"]) <= 1e-6 * m["mass0"]
+    bound = 4 * np.finfo(np.float32).eps * 5.0 * np.sqrt(m["nsite"] * 20.0)
+    print(f"[mass] D3Q7 512^3 fp32: drift {m['mass'] - m['mass0']:.3e} (bound {bound:.3e})")
+    assert abs(m["mass"] - m["mass0"]) <= bound
     L.close()
 
 
