@@ -202,8 +202,11 @@ typedef struct {
   int32_t chunk;        /* steps per graph (>= 1); 0 -> 16 */
   int32_t use_graph;    /* 1 = capture chunks in a HIP graph, 0 = eager launches */
   int32_t lds_max_bytes;/* largest D1Q3 state run LDS-resident; 0 -> 64 KiB, -1 = never */
-  int32_t workers;      /* persistent workgroups; 0 -> 4 per CU */
-  void* hip_stream;     /* stream of all batch work (NULL = null stream) */
+  int32_t workers;      /* 0: one workgroup per work item; > 0: a persistent grid of
+                           this many workgroups striding over the items */
+  int32_t item_rows;    /* rows per work item of the HBM kernel: 2, 4, 8, 16; 0 -> 2 */
+  int32_t reserved;     /* must be 0 */
+  void* hip_stream;     /* stream of all batch work (NULL = a stream of its own) */
 } flb_batch_opts;
 
 int flb_batch_create(const flb_batch_opts* opts, flb_batch** out);

@@ -1,5 +1,5 @@
 // Batched ensembles: many lattices of uneven size and dimension advanced by
-// one persistent work-list launch per step (lattices in HBM) and one
+// one work-list launch per step (lattices in HBM) and one
 // LDS-resident launch per chunk of steps (small D1Q3 lattices), the chunk
 // captured once into a HIP graph and replayed.  Every member's arithmetic,
 // noise keys and storage order are those of flb_step on the member alone,
@@ -32,11 +32,15 @@ struct BatchRep {
   int32_t pad;
 };
 
-constexpr int kBatchTX = 256;  // tile width of the work-list kernel
-constexpr int kBatchRY = 2;    // rows per tile
+// A work item is a tile of kBatchTX columns x `rows` rows (a multiple of
+// kBatchRY), run by one kBatchTX-thread workgroup in sub-tiles of kBatchRY
+// rows; taller items spread the item's descriptor loads over more sites.
+constexpr int kBatchTX = 256;
+constexpr int kBatchRY = 2;
 
-// Persistent work list: item w is tile item_tile[w] of member item_rep[w].
-template <int D, typename T>
+// Work list: item w is tile item_tile[w] of member item_rep[w]; with a grid
+// smaller than the list the workgroups persist and stride over it.
+template <int D, typename T, int SUB>
 __global__ void __launch_bounds__(kBatchTX) k_batch_rows(const BatchRep<T>* __restrict__ reps,
                                                          const int32_t* __restrict__ item_rep,
                                                          const int32_t* __restrict__ item_tile,
@@ -50,7 +54,11 @@ __global__ void __launch_bounds__(kBatchTX) k_batch_rows(const BatchRep<T>* __re
     const int par = (R.cur0 + k) & 1;
     const T* g = (const T*)(R.pop + par * R.plane);
     T* h = (T*)(R.pop + (par ^ 1) * R.plane);
-    rows_tile<D, T, kBatchRY, true>(g, h, P, step, tile % R.tiles_x, tile / R.tiles_x, R.nrows);
+    const int64_t tx = tile % R.tiles_x, tr = tile / R.tiles_x;
+    const uint32_t x = (uint32_t)(tx * kBatchTX) + threadIdx.x;
+#pragma unroll
+    for (int sub = 0; sub < SUB; ++sub)
+      rows_tile<D, T, kBatchRY, true>(g, h, P, step, x, (tr * SUB + sub) * kBatchRY, R.nrows);
   }
 }
 
@@ -148,6 +156,7 @@ struct flb_batch {
   int nlds, lds_spt;
   size_t lds_bytes;
   int nreps;
+  int sub;  // sub-tiles of kBatchRY rows per work item
   hipGraphExec_t exec;
   int exec_chunk;
 };
@@ -208,7 +217,8 @@ int rebuild_t(flb_batch* b) {
       lmax = std::max<int64_t>(lmax, h->n);
       continue;
     }
-    const int64_t ntile = R.tiles_x * ((R.nrows + kBatchRY - 1) / kBatchRY);
+    const int64_t item_rows = (int64_t)kBatchRY * b->sub;
+    const int64_t ntile = R.tiles_x * ((R.nrows + item_rows - 1) / item_rows);
     if (ntile >= (1ll << 31)) return fail(FLB_EINVAL, "member %d has too many tiles", i);
     for (int64_t t = 0; t < ntile; ++t) {
       items[h->d][0].push_back(i);
@@ -264,17 +274,28 @@ void enqueue_chunk_t(flb_batch* b, int c) {
       default: k_batch_lds_d1<T, 16><<<grid, block, b->lds_bytes, st>>>(reps, lr, c); break;
     }
   }
-  const int workers_per_cu = b->o.workers > 0 ? 0 : 8;
   for (int k = 0; k < c; ++k) {
     for (int d = 1; d <= 3; ++d) {
       const int ni = b->nitems[d];
       if (ni == 0) continue;
-      const int grid = std::max(1, std::min(ni, b->o.workers > 0 ? b->o.workers : workers_per_cu * b->ncu));
+      // workers == 0: one workgroup per item, the dispatcher balances; else a
+      // persistent grid of `workers` workgroups strides over the items
+      const int grid = b->o.workers > 0 ? std::max(1, std::min(ni, b->o.workers)) : ni;
       const int32_t* ir = (const int32_t*)(b->d_table + b->off_items[d][0]);
       const int32_t* it = (const int32_t*)(b->d_table + b->off_items[d][1]);
-      if (d == 1) k_batch_rows<1, T><<<grid, kBatchTX, 0, st>>>(reps, ir, it, ni, k);
-      else if (d == 2) k_batch_rows<2, T><<<grid, kBatchTX, 0, st>>>(reps, ir, it, ni, k);
-      else k_batch_rows<3, T><<<grid, kBatchTX, 0, st>>>(reps, ir, it, ni, k);
+#define FLB_BATCH_ROWS(SUBV)                                                                   \
+  do {                                                                                         \
+    if (d == 1) k_batch_rows<1, T, SUBV><<<grid, kBatchTX, 0, st>>>(reps, ir, it, ni, k);      \
+    else if (d == 2) k_batch_rows<2, T, SUBV><<<grid, kBatchTX, 0, st>>>(reps, ir, it, ni, k); \
+    else k_batch_rows<3, T, SUBV><<<grid, kBatchTX, 0, st>>>(reps, ir, it, ni, k);             \
+  } while (0)
+      switch (b->sub) {
+        case 1: FLB_BATCH_ROWS(1); break;
+        case 2: FLB_BATCH_ROWS(2); break;
+        case 4: FLB_BATCH_ROWS(4); break;
+        default: FLB_BATCH_ROWS(8); break;
+      }
+#undef FLB_BATCH_ROWS
     }
   }
   k_batch_advance<T><<<(b->nreps + 255) / 256, 256, 0, st>>>((BatchRep<T>*)b->d_table, b->nreps, c);
@@ -314,6 +335,8 @@ int flb_batch_create(const flb_batch_opts* opts, flb_batch** out) {
   if (o.chunk < 0 || o.chunk > 4096) return fail(FLB_EINVAL, "chunk must be in [0, 4096]");
   if (o.workers < 0) return fail(FLB_EINVAL, "workers must be >= 0");
   if (o.lds_max_bytes > 65536) return fail(FLB_EINVAL, "lds_max_bytes must be <= 65536");
+  if (o.item_rows != 0 && o.item_rows != 2 && o.item_rows != 4 && o.item_rows != 8 && o.item_rows != 16)
+    return fail(FLB_EINVAL, "item_rows must be 2, 4, 8 or 16");
   if (o.chunk == 0) o.chunk = 16;
   flb_batch* b = new (std::nothrow) flb_batch();
   if (!b) return fail(FLB_ENOMEM, "batch allocation failed");
@@ -326,6 +349,7 @@ int flb_batch_create(const flb_batch_opts* opts, flb_batch** out) {
   b->exec_chunk = 0;
   b->nlds = 0;
   b->nreps = 0;
+  b->sub = o.item_rows ? o.item_rows / kBatchRY : 1;
   for (int d = 0; d < 4; ++d) b->nitems[d] = 0;
   hipError_t e = hipGetDevice(&b->device);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, b->device);

@@ -104,21 +104,20 @@ __device__ __forceinline__ void st_at(T* __restrict__ base, uint32_t byte_off, T
 // populations are loaded before any is collided, so that every wave keeps
 // RY * Q loads in flight; NT selects non-temporal stores (the new state is
 // not re-read within this launch).
+// Column x of rows row0 .. row0 + RY - 1 (row0 is uniform over a wave).
 template <int D, typename T, int RY, bool NT>
 __device__ __forceinline__ void rows_tile(const T* __restrict__ g, T* __restrict__ h,
-                                          const KParams<T>& P, uint32_t step, int64_t tx,
-                                          int64_t tr, int64_t nrows) {
+                                          const KParams<T>& P, uint32_t step, uint32_t x,
+                                          int64_t row0, int64_t nrows) {
   constexpr int Q = 2 * D + 1;
-  // the row tile and every plane/row base are uniform over the block (scalar
+  // the row tile and every plane/row base are uniform over the wave (scalar
   // registers); per lane only 32-bit column offsets remain
   const uint32_t nx = (uint32_t)P.nx;
-  const uint32_t x = (uint32_t)(tx * blockDim.x) + threadIdx.x;
   if (x >= nx) return;
   const int64_t n = P.n;
   constexpr uint32_t S = sizeof(T);
   const uint32_t bx = x * S;                                   // nx * S < 2^32
   const uint32_t bxm = (x == 0 ? nx - 1 : x - 1) * S, bxp = (x == nx - 1 ? 0 : x + 1) * S;
-  const int64_t row0 = tr * RY;
   T f[RY][Q];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
@@ -168,7 +167,8 @@ __global__ void __launch_bounds__(1024) k_step_rows(const T* __restrict__ g, T* 
                                                     int64_t nrows, int remap) {
   const int64_t G = (int64_t)gridDim.x;
   const int64_t tile = remap ? xcd_tile(blockIdx.x, G) : (int64_t)blockIdx.x;
-  rows_tile<D, T, RY, NT>(g, h, P, step, tile % tiles_x, tile / tiles_x, nrows);
+  const int64_t tx = tile % tiles_x, tr = tile / tiles_x;
+  rows_tile<D, T, RY, NT>(g, h, P, step, (uint32_t)(tx * blockDim.x) + threadIdx.x, tr * RY, nrows);
 }
 
 // ---------------------------------------------------------------------------
