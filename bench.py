@@ -23,6 +23,28 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step_d2q5_4096_fp32_traffic.md")
+
+
+def measured_traffic():
+    """HBM bytes per step launch from the committed counter summary, or None
+    if the step kernel's sources changed since the counters were taken."""
+    import hashlib
+    try:
+        vals = {}
+        for line in open(TRAFFIC_PROFILE):
+            if ":" in line and not line.startswith(("#", "|", " ", "`")):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+        h = hashlib.sha256()
+        for f in ("flb_device.hpp", "flb_kernels.hpp"):
+            with open(os.path.join(ROOT, "paper_1606_07801_amd", "csrc", f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest()[:16] != vals.get("kernel_source_sha256_16"):
+            return None
+        return int(float(vals["traffic_bytes_per_launch"]))
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -35,6 +57,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--requests", type=int, default=48, help="served workload: number of requests")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--workload", default="lattice", choices=["lattice", "d1q3", "d3q7", "batched", "served"],
                     help="lattice: the D2Q5 4096^2 line (default); the others print their own line")
     return ap.parse_args()
@@ -120,7 +144,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(),
             "kernel": "k_step_rows<2,float>", "kernel_us": round(kern_ms * 1e3, 2),
             "bytes_per_launch": bytes_per_launch,
         },
@@ -140,6 +164,21 @@ def main():
         P.close()
         out["fp64_plain"] = {"mlups": round(N / (ms64 * 1e-3) / 1e6, 1), "ms_per_step": round(ms64, 4),
                              "hbm_gbs": round(2 * Q * 8 * N / (kern64 * 1e-3) / 1e9, 1)}
+
+    if args.copy_probe_mib:
+        nb = args.copy_probe_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 10
+        out["copy_probe"] = {"bytes_each_way": nb, "gbs_read_plus_write": round(2 * nb / dt / 1e9, 1)}
+        del src, dst
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(flb, inputs, n, f0)
