@@ -64,7 +64,7 @@ enum { FLB_LAW_GAUSS = 0, FLB_LAW_UNIFORM = 1 };
 /* storage scheme: two buffers with pull streaming (the only one so far) */
 enum { FLB_LAYOUT_TWO_BUFFER = 0 };
 /* kernel variants of the step (all give bit-identical results) */
-enum { FLB_KERNEL_AUTO = 0, FLB_KERNEL_PLAIN = 1, FLB_KERNEL_ROWS = 2 };
+enum { FLB_KERNEL_AUTO = 0, FLB_KERNEL_PLAIN = 1, FLB_KERNEL_ROWS = 2, FLB_KERNEL_FLAT = 3 };
 
 typedef struct flb_lattice flb_lattice; /* opaque */
 typedef struct flb_batch flb_batch;     /* opaque */
@@ -87,7 +87,9 @@ typedef struct {
                          of 64); 0 -> default */
   int32_t tile_rows;  /* rows kernel: rows per thread (1, 2, 4, 8, 16); 0 -> default */
   int32_t nt_store;   /* rows kernel: 1 = non-temporal stores of the new state */
-  int32_t reserved;   /* must be 0 */
+  int32_t pipeline;   /* rows kernel: 1 = rows software-pipelined (next row's loads in
+                         flight while the current row is collided), 0 = all rows of a
+                         tile loaded first */
 } flb_params;
 
 typedef struct {
@@ -173,6 +175,15 @@ int flb_moments(flb_lattice* h, flb_moments_t* out);
 int flb_structure_factor(flb_lattice* h, const int32_t* kvec, int32_t nk, int32_t mode,
                          double* S_out);
 
+/* Sample the structure factor while stepping: from now on, flb_step
+ * accumulates S(k) of the state before every step t with t % every == 0 into
+ * the accumulator (read with FLB_SK_READ), for the k-list kvec (nk x 3, as
+ * for flb_structure_factor).  Resets the accumulator.  When every wave vector
+ * lies on an axis (or is zero) and the lattice is 2-D or 3-D, the sampled
+ * step itself accumulates the density marginals (no extra pass over the
+ * populations).  every = 0 stops sampling (kvec may be NULL). */
+int flb_set_sampling(flb_lattice* h, int64_t every, const int32_t* kvec, int32_t nk);
+
 /* Block until the handle's stream has finished. */
 int flb_sync(flb_lattice* h);
 
@@ -204,8 +215,10 @@ typedef struct {
   int32_t lds_max_bytes;/* largest D1Q3 state run LDS-resident; 0 -> 64 KiB, -1 = never */
   int32_t workers;      /* 0: one workgroup per work item; > 0: a persistent grid of
                            this many workgroups striding over the items */
-  int32_t item_rows;    /* rows per work item of the HBM kernel: 2, 4, 8, 16; 0 -> 2 */
-  int32_t reserved;     /* must be 0 */
+  int32_t item_rows;    /* row tiling: rows per work item, 2, 4, 8, 16; 0 -> 2 */
+  int32_t tiling;       /* work items of the HBM kernel: 0 = 512 consecutive sites of a
+                           member (lanes filled across row ends), 1 = 256 x item_rows
+                           row tiles */
   void* hip_stream;     /* stream of all batch work (NULL = a stream of its own) */
 } flb_batch_opts;
 

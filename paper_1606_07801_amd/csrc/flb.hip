@@ -75,10 +75,13 @@ int check_params(const flb_params* p) {
   if (p->noise < 0 || p->noise > 2) return fail(FLB_EINVAL, "noise must be 0 (local), 1 (global) or 2 (off)");
   if (p->noise_law < 0 || p->noise_law > 1) return fail(FLB_EINVAL, "noise_law must be 0 (Gauss) or 1 (uniform)");
   if (p->layout != FLB_LAYOUT_TWO_BUFFER) return fail(FLB_EINVAL, "layout must be FLB_LAYOUT_TWO_BUFFER");
-  if (p->kernel < 0 || p->kernel > 2) return fail(FLB_EINVAL, "kernel must be 0 (auto), 1 (plain) or 2 (rows)");
+  if (p->kernel < 0 || p->kernel > 3) return fail(FLB_EINVAL, "kernel must be 0 (auto), 1 (plain), 2 (rows) or 3 (flat)");
+  if (p->kernel == FLB_KERNEL_FLAT && (p->tile_rows > 8 || n * (2 * d + 1) * p->precision >= 4294967296.0))
+    return fail(FLB_EINVAL, "flat kernel: tile_rows <= 8 and Q * N * precision < 2^32");
   if (p->tile_x != 0 && (p->tile_x < 64 || p->tile_x > 1024 || p->tile_x % 64 != 0))
     return fail(FLB_EINVAL, "tile_x must be a multiple of 64 in [64, 1024]");
   if (p->nt_store != 0 && p->nt_store != 1) return fail(FLB_EINVAL, "nt_store must be 0 or 1");
+  if (p->pipeline != 0 && p->pipeline != 1) return fail(FLB_EINVAL, "pipeline must be 0 or 1");
   if (p->tile_rows != 0 && p->tile_rows != 1 && p->tile_rows != 2 && p->tile_rows != 4 &&
       p->tile_rows != 8 && p->tile_rows != 16)
     return fail(FLB_EINVAL, "tile_rows must be 1, 2, 4, 8 or 16");
@@ -142,6 +145,9 @@ WorkLayout work_layout(const flb_params& p) {
     L.rowsum = take(sizeof(double) * nrows);
     L.colpart = take(sizeof(double) * std::min<int64_t>(kColChunks, nrows) * nx);
     L.marg = take(sizeof(double) * (nx + ny + nz));
+    L.tw = take(sizeof(double) * 2 * (nx + ny + nz));
+    L.rowpart = take(sizeof(double) * ((nx + 255) / 256) * nrows);
+    L.colbig = take(sizeof(double) * ((nrows + kSampleRows - 1) / kSampleRows) * nx);
   }
   L.skpart = take(sizeof(double) * 2 * (size_t)kMaxK * kSkChunks);
   for (int s = 0; s < 2; ++s) {
@@ -171,6 +177,20 @@ int launch_step_t(flb_lattice* h, const T* g, T* out, uint32_t step, hipStream_t
   if (kern == FLB_KERNEL_PLAIN) {
     const int64_t nb = (h->n + 255) / 256;
     k_step_plain<D, T><<<dim3((unsigned)nb), dim3(256), 0, st>>>(g, out, P, step);
+  } else if (kern == FLB_KERNEL_FLAT) {
+    const int ry = h->p.tile_rows ? h->p.tile_rows : 2;
+    const int64_t nb = (h->n + 256 * ry - 1) / (256 * ry);
+    const bool nt = h->p.nt_store != 0;
+#define FLB_FLAT(RYV)                                                                     \
+  (nt ? (void)(k_step_flat<D, T, RYV, true><<<(unsigned)nb, 256, 0, st>>>(g, out, P, step)) \
+      : (void)(k_step_flat<D, T, RYV, false><<<(unsigned)nb, 256, 0, st>>>(g, out, P, step)))
+    switch (ry) {
+      case 1: FLB_FLAT(1); break;
+      case 2: FLB_FLAT(2); break;
+      case 4: FLB_FLAT(4); break;
+      default: FLB_FLAT(8); break;
+    }
+#undef FLB_FLAT
   } else {
     const int bx = h->p.tile_x ? h->p.tile_x : 256;
     const int ry = D == 1 ? 1 : (h->p.tile_rows ? h->p.tile_rows : 4);
@@ -181,9 +201,12 @@ int launch_step_t(flb_lattice* h, const T* g, T* out, uint32_t step, hipStream_t
     const int remap = 1;
     dim3 grid((unsigned)G), block((unsigned)bx);
     const bool nt = h->p.nt_store != 0;
-#define FLB_ROWS(RYV)                                                                             \
-  (nt ? (void)(k_step_rows<D, T, RYV, true><<<grid, block, 0, st>>>(g, out, P, step, tiles_x, nrows, remap)) \
-      : (void)(k_step_rows<D, T, RYV, false><<<grid, block, 0, st>>>(g, out, P, step, tiles_x, nrows, remap)))
+    const bool pipe = h->p.pipeline != 0;
+#define FLB_ROWS(RYV)                                                                                    \
+  (pipe ? (nt ? (void)(k_step_rows<D, T, RYV, true, true><<<grid, block, 0, st>>>(g, out, P, step, tiles_x, nrows, remap))   \
+              : (void)(k_step_rows<D, T, RYV, false, true><<<grid, block, 0, st>>>(g, out, P, step, tiles_x, nrows, remap)))  \
+        : (nt ? (void)(k_step_rows<D, T, RYV, true><<<grid, block, 0, st>>>(g, out, P, step, tiles_x, nrows, remap))         \
+              : (void)(k_step_rows<D, T, RYV, false><<<grid, block, 0, st>>>(g, out, P, step, tiles_x, nrows, remap))))
     switch (ry) {
       case 1: FLB_ROWS(1); break;
       case 2: FLB_ROWS(2); break;
@@ -294,8 +317,32 @@ void classify_k(const flb_lattice* h, const int32_t* kvec, int nk, KStage* st, i
   *ngen = ng;
 }
 
+// Axis marginals from rowsum / colpart (nchunk chunks), then the axis DFTs.
+void axis_sk(flb_lattice* h, int set, int64_t nchunk) {
+  const int64_t nx = h->p.n[0], ny = h->p.n[1], nz = h->p.n[2];
+  hipStream_t st = h->stream;
+  char* w = h->work;
+  double* rowsum = (double*)(w + h->wl.rowsum);
+  double* colpart = (double*)(w + h->wl.colpart);
+  double* mx = (double*)(w + h->wl.marg);
+  double* my = mx + nx;
+  double* mz = my + ny;
+  const double* tw = (const double*)(w + h->wl.tw);
+  k_marginal_x<<<(unsigned)((nx + 63) / 64), 256, 0, st>>>(colpart, nchunk, nx, mx);
+  k_marginal_y<<<(unsigned)((ny + 255) / 256), 256, 0, st>>>(rowsum, ny, nz, my);
+  if (h->d == 3) k_marginal_z<<<(unsigned)nz, 256, 0, st>>>(rowsum, ny, mz);
+  k_sk_axis<<<(unsigned)h->nax[set], 256, 0, st>>>(mx, my, mz, nx, ny, nz,
+                                                   (const int64_t*)(w + h->wl.kinfo[set]),
+                                                   (const int32_t*)(w + h->wl.slot_ax[set]), tw,
+                                                   tw + 2 * nx, tw + 2 * (nx + ny),
+                                                   (double*)(w + h->wl.sval[set]));
+}
+
+// S(k) of the current state for k-list `set`.  from_step: the axis
+// partials were written by the sampled step (colbig / rowpart) and only need
+// to be reduced.
 template <int D, typename T>
-void launch_sk_t(flb_lattice* h, int set) {
+void launch_sk_t(flb_lattice* h, int set, bool from_step) {
   const T* g = (const T*)flb::lat_buffer(h, h->cur);
   const int64_t nx = h->p.n[0], ny = h->p.n[1], nz = h->p.n[2];
   hipStream_t st = h->stream;
@@ -307,18 +354,19 @@ void launch_sk_t(flb_lattice* h, int set) {
     const int64_t rpc = (nrows + nchunk - 1) / nchunk;
     double* rowsum = (double*)(w + h->wl.rowsum);
     double* colpart = (double*)(w + h->wl.colpart);
-    double* mx = (double*)(w + h->wl.marg);
-    double* my = mx + nx;
-    double* mz = my + ny;
-    k_row_sums<D, T><<<(unsigned)nrows, 256, 0, st>>>(g, nx, ny, nz, rowsum);
-    k_col_partial<D, T><<<dim3((unsigned)((nx + 255) / 256), (unsigned)nchunk), 256, 0, st>>>(g, nx, ny, nz, rpc, colpart);
-    k_marginals_xy<<<(unsigned)((nx + ny + 255) / 256), 256, 0, st>>>(colpart, nchunk, rowsum, nx, ny, nz, mx, my);
-    if (D == 3) k_marginal_z<<<(unsigned)nz, 256, 0, st>>>(rowsum, ny, mz);
-    k_sk_axis<<<(unsigned)h->nax[set], 256, 0, st>>>(mx, my, mz, nx, ny, nz,
-                                                     (const int64_t*)(w + h->wl.kinfo[set]),
-                                                     (const int32_t*)(w + h->wl.slot_ax[set]), sval);
+    if (from_step) {
+      const int64_t ntx = (nx + 255) / 256, ntr = (nrows + kSampleRows - 1) / kSampleRows;
+      k_rowpart_reduce<<<(unsigned)((nrows + 255) / 256), 256, 0, st>>>((const double*)(w + h->wl.rowpart), ntx, nrows, rowsum);
+      k_colpart_reduce<<<dim3((unsigned)((nx + 255) / 256), (unsigned)nchunk), 256, 0, st>>>(
+          (const double*)(w + h->wl.colbig), ntr, nx, nchunk, colpart);
+    }
+    if (!from_step) {
+      k_row_sums<D, T><<<(unsigned)nrows, 256, 0, st>>>(g, nx, ny, nz, rowsum);
+      k_col_partial<D, T><<<dim3((unsigned)((nx + 255) / 256), (unsigned)nchunk), 256, 0, st>>>(g, nx, ny, nz, rpc, colpart);
+    }
+    axis_sk(h, set, nchunk);
   }
-  if (h->ngen[set] > 0) {
+  if (h->ngen[set] > 0 && !from_step) {
     const int64_t nchunk = std::min<int64_t>(kSkChunks, (h->n + 255) / 256);
     const int64_t chunk = (h->n + nchunk - 1) / nchunk;
     double* part = (double*)(w + h->wl.skpart);
@@ -330,16 +378,44 @@ void launch_sk_t(flb_lattice* h, int set) {
   }
 }
 
-void launch_sk(flb_lattice* h, int set) {
+void launch_sk(flb_lattice* h, int set, bool from_step = false) {
   if (h->s == 4) {
-    if (h->d == 1) launch_sk_t<1, float>(h, set);
-    else if (h->d == 2) launch_sk_t<2, float>(h, set);
-    else launch_sk_t<3, float>(h, set);
+    if (h->d == 1) launch_sk_t<1, float>(h, set, from_step);
+    else if (h->d == 2) launch_sk_t<2, float>(h, set, from_step);
+    else launch_sk_t<3, float>(h, set, from_step);
   } else {
-    if (h->d == 1) launch_sk_t<1, double>(h, set);
-    else if (h->d == 2) launch_sk_t<2, double>(h, set);
-    else launch_sk_t<3, double>(h, set);
+    if (h->d == 1) launch_sk_t<1, double>(h, set, from_step);
+    else if (h->d == 2) launch_sk_t<2, double>(h, set, from_step);
+    else launch_sk_t<3, double>(h, set, from_step);
   }
+}
+
+// The sampled step (D >= 2): step + axis partials of the pre-collision state.
+template <int D, typename T>
+void launch_step_sampled_t(flb_lattice* h, const T* g, T* out, uint32_t step) {
+  const KParams<T> P = make_kparams<T>(h->p, h->rho_eq);
+  const int64_t nrows = P.ny * P.nz;
+  const int64_t tiles_x = (P.nx + 255) / 256;
+  const int64_t G = tiles_x * ((nrows + kSampleRows - 1) / kSampleRows);
+  k_step_rows_sk<D, T, kSampleRows><<<(unsigned)G, 256, 0, h->stream>>>(
+      g, out, P, step, tiles_x, nrows, (double*)(h->work + h->wl.rowpart), (double*)(h->work + h->wl.colbig));
+}
+
+void launch_step_sampled(flb_lattice* h, const void* g, void* out, uint32_t step) {
+  if (h->s == 4) {
+    if (h->d == 2) launch_step_sampled_t<2, float>(h, (const float*)g, (float*)out, step);
+    else launch_step_sampled_t<3, float>(h, (const float*)g, (float*)out, step);
+  } else {
+    if (h->d == 2) launch_step_sampled_t<2, double>(h, (const double*)g, (double*)out, step);
+    else launch_step_sampled_t<3, double>(h, (const double*)g, (double*)out, step);
+  }
+}
+
+void sk_accumulate(flb_lattice* h) {
+  char* w = h->work;
+  k_sk_accumulate<<<(h->nk[1] + 255) / 256, 256, 0, h->stream>>>((const double*)(w + h->wl.sval[1]),
+                                                                 (double*)(w + h->wl.skacc), h->nk[1]);
+  h->sk_count += 1;
 }
 
 // Upload a k-list into set `set` of the workspace; synchronises.
@@ -475,6 +551,17 @@ int flb_create(const flb_params* p, void* d_pop, size_t pop_bytes, void* d_work,
     }
     h->own_work = true;
   }
+  h->sample_every = 0;
+  h->sample_fused = false;
+  if (h->d >= 2) {  // twiddle tables of the axis structure factor
+    double* tw = (double*)(h->work + h->wl.tw);
+    const int64_t L3[3] = {p->n[0], p->n[1], p->n[2]};
+    int64_t off = 0;
+    for (int a = 0; a < 3; ++a) {
+      k_twiddle<<<(unsigned)((L3[a] + 255) / 256), 256, 0, h->stream>>>(tw + 2 * off, L3[a]);
+      off += L3[a];
+    }
+  }
   e = hipHostMalloc((void**)&h->stage, sizeof(KStage), hipHostMallocDefault);
   if (e != hipSuccess) {
     if (h->own_work) (void)hipFree(h->work);
@@ -538,7 +625,19 @@ int flb_step(flb_lattice* h, int64_t nsteps) {
   DeviceGuard g(h->device);
   for (int64_t k = 0; k < nsteps; ++k) {
     const int nxt = 1 - h->cur;
-    launch_step(h, lat_buffer(h, h->cur), lat_buffer(h, nxt), (uint32_t)(h->step & 0xFFFFFFFF), h->stream);
+    const uint32_t t32 = (uint32_t)(h->step & 0xFFFFFFFF);
+    const bool sample = h->sample_every > 0 && h->step % h->sample_every == 0;
+    if (sample && h->sample_fused) {
+      launch_step_sampled(h, lat_buffer(h, h->cur), lat_buffer(h, nxt), t32);
+      launch_sk(h, 1, true);
+      sk_accumulate(h);
+    } else {
+      if (sample) {  // S(k) of the state before this step, then the step
+        launch_sk(h, 1);
+        sk_accumulate(h);
+      }
+      launch_step(h, lat_buffer(h, h->cur), lat_buffer(h, nxt), t32, h->stream);
+    }
     h->cur = nxt;
     h->step += 1;
   }
@@ -609,10 +708,8 @@ int flb_structure_factor(flb_lattice* h, const int32_t* kvec, int32_t nk, int32_
     if (kvec && (nk != h->nk[1] || std::memcmp(kvec, h->klist[1].data(), sizeof(int32_t) * 3 * nk) != 0))
       return fail(FLB_EINVAL, "SAMPLE k-list differs from the one given at RESET");
     launch_sk(h, 1);
-    k_sk_accumulate<<<(h->nk[1] + 255) / 256, 256, 0, h->stream>>>((const double*)(w + h->wl.sval[1]),
-                                                                   (double*)(w + h->wl.skacc), h->nk[1]);
+    sk_accumulate(h);
     HIP_TRY(hipGetLastError());
-    h->sk_count += 1;
     return FLB_OK;
   }
   // READ
@@ -621,6 +718,22 @@ int flb_structure_factor(flb_lattice* h, const int32_t* kvec, int32_t nk, int32_
   HIP_TRY(hipMemcpyAsync(h->stage->out, w + h->wl.skacc, sizeof(double) * h->nk[1], hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   for (int j = 0; j < h->nk[1]; ++j) S_out[j] = h->stage->out[j] / (double)h->sk_count;
+  return FLB_OK;
+}
+
+int flb_set_sampling(flb_lattice* h, int64_t every, const int32_t* kvec, int32_t nk) {
+  if (!h) return fail(FLB_EINVAL, "NULL handle");
+  if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
+  if (every < 0) return fail(FLB_EINVAL, "every must be >= 0");
+  if (every == 0) {
+    h->sample_every = 0;
+    return FLB_OK;
+  }
+  DeviceGuard g(h->device);
+  const int rc = flb_structure_factor(h, kvec, nk, FLB_SK_RESET, nullptr);
+  if (rc) return rc;
+  h->sample_every = every;
+  h->sample_fused = h->d >= 2 && h->ngen[1] == 0;
   return FLB_OK;
 }
 

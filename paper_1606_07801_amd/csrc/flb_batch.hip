@@ -40,6 +40,26 @@ constexpr int kBatchRY = 2;
 
 // Work list: item w is tile item_tile[w] of member item_rep[w]; with a grid
 // smaller than the list the workgroups persist and stride over it.
+// Flat work list: item w covers sites item_tile[w] * 256 * kBatchRY ... of
+// member item_rep[w] (flat_tile), so narrow lattices keep every lane busy.
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_batch_flat(const BatchRep<T>* __restrict__ reps,
+                                                    const int32_t* __restrict__ item_rep,
+                                                    const int32_t* __restrict__ item_tile,
+                                                    int nitems, int k) {
+  for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+    const int r = __builtin_amdgcn_readfirstlane(item_rep[w]);
+    const int64_t tile = __builtin_amdgcn_readfirstlane(item_tile[w]);
+    const BatchRep<T>& R = reps[r];
+    const KParams<T> P = R.P;
+    const uint32_t step = (uint32_t)((uint64_t)(R.step0 + k) & 0xFFFFFFFFull);
+    const int par = (R.cur0 + k) & 1;
+    const T* g = (const T*)(R.pop + par * R.plane);
+    T* h = (T*)(R.pop + (par ^ 1) * R.plane);
+    flat_tile<D, T, kBatchRY, true>(g, h, P, step, tile * 256 * kBatchRY, threadIdx.x);
+  }
+}
+
 template <int D, typename T, int SUB>
 __global__ void __launch_bounds__(kBatchTX) k_batch_rows(const BatchRep<T>* __restrict__ reps,
                                                          const int32_t* __restrict__ item_rep,
@@ -150,8 +170,8 @@ struct flb_batch {
   // device table: reps, then the item lists and the LDS member list
   char* d_table;
   size_t table_cap;
-  size_t off_items[4][2];  // per dimension class 1..3: item_rep, item_tile
-  int nitems[4];
+  size_t off_items[7][2];  // per class (d = 1..3 row tiles, d + 3 flat tiles): item_rep, item_tile
+  int nitems[7];
   size_t off_lds;
   int nlds, lds_spt;
   size_t lds_bytes;
@@ -196,7 +216,7 @@ template <typename T>
 int rebuild_t(flb_batch* b) {
   const int n = (int)b->members.size();
   std::vector<BatchRep<T>> reps(n);
-  std::vector<int32_t> items[4][2];
+  std::vector<int32_t> items[7][2];
   std::vector<int32_t> lds;
   int64_t lmax = 0;
   const int64_t lds_max = b->o.lds_max_bytes < 0 ? -1 : (b->o.lds_max_bytes ? b->o.lds_max_bytes : 65536);
@@ -218,15 +238,19 @@ int rebuild_t(flb_batch* b) {
       continue;
     }
     const int64_t item_rows = (int64_t)kBatchRY * b->sub;
-    const int64_t ntile = R.tiles_x * ((R.nrows + item_rows - 1) / item_rows);
+    const bool flat = b->o.tiling == 0 && (int64_t)h->plane < (1ll << 32);
+    if (flat) R.tiles_x = -1;  // marks a flat member
+    const int64_t ntile = flat ? (h->n + 256 * kBatchRY - 1) / (256 * kBatchRY)
+                               : R.tiles_x * ((R.nrows + item_rows - 1) / item_rows);
     if (ntile >= (1ll << 31)) return fail(FLB_EINVAL, "member %d has too many tiles", i);
+    const int cls = h->d + (flat ? 3 : 0);
     for (int64_t t = 0; t < ntile; ++t) {
-      items[h->d][0].push_back(i);
-      items[h->d][1].push_back((int32_t)t);
+      items[cls][0].push_back(i);
+      items[cls][1].push_back((int32_t)t);
     }
   }
   size_t o = align256(sizeof(BatchRep<T>) * std::max(n, 1));
-  for (int d = 1; d <= 3; ++d) {
+  for (int d = 1; d <= 6; ++d) {
     b->nitems[d] = (int)items[d][0].size();
     b->off_items[d][0] = o;
     o += align256(sizeof(int32_t) * std::max<size_t>(items[d][0].size(), 1));
@@ -243,7 +267,7 @@ int rebuild_t(flb_batch* b) {
     b->table_cap = o;
   }
   HIP_TRY(hipMemcpy(b->d_table, reps.data(), sizeof(BatchRep<T>) * n, hipMemcpyHostToDevice));
-  for (int d = 1; d <= 3; ++d)
+  for (int d = 1; d <= 6; ++d)
     for (int k = 0; k < 2; ++k)
       if (!items[d][k].empty())
         HIP_TRY(hipMemcpy(b->d_table + b->off_items[d][k], items[d][k].data(),
@@ -275,6 +299,16 @@ void enqueue_chunk_t(flb_batch* b, int c) {
     }
   }
   for (int k = 0; k < c; ++k) {
+    for (int d = 4; d <= 6; ++d) {  // flat members
+      const int ni = b->nitems[d];
+      if (ni == 0) continue;
+      const int grid = b->o.workers > 0 ? std::max(1, std::min(ni, b->o.workers)) : ni;
+      const int32_t* ir = (const int32_t*)(b->d_table + b->off_items[d][0]);
+      const int32_t* it = (const int32_t*)(b->d_table + b->off_items[d][1]);
+      if (d == 4) k_batch_flat<1, T><<<grid, 256, 0, st>>>(reps, ir, it, ni, k);
+      else if (d == 5) k_batch_flat<2, T><<<grid, 256, 0, st>>>(reps, ir, it, ni, k);
+      else k_batch_flat<3, T><<<grid, 256, 0, st>>>(reps, ir, it, ni, k);
+    }
     for (int d = 1; d <= 3; ++d) {
       const int ni = b->nitems[d];
       if (ni == 0) continue;
@@ -335,6 +369,7 @@ int flb_batch_create(const flb_batch_opts* opts, flb_batch** out) {
   if (o.chunk < 0 || o.chunk > 4096) return fail(FLB_EINVAL, "chunk must be in [0, 4096]");
   if (o.workers < 0) return fail(FLB_EINVAL, "workers must be >= 0");
   if (o.lds_max_bytes > 65536) return fail(FLB_EINVAL, "lds_max_bytes must be <= 65536");
+  if (o.tiling < 0 || o.tiling > 1) return fail(FLB_EINVAL, "tiling must be 0 (flat) or 1 (rows)");
   if (o.item_rows != 0 && o.item_rows != 2 && o.item_rows != 4 && o.item_rows != 8 && o.item_rows != 16)
     return fail(FLB_EINVAL, "item_rows must be 2, 4, 8 or 16");
   if (o.chunk == 0) o.chunk = 16;
@@ -350,7 +385,7 @@ int flb_batch_create(const flb_batch_opts* opts, flb_batch** out) {
   b->nlds = 0;
   b->nreps = 0;
   b->sub = o.item_rows ? o.item_rows / kBatchRY : 1;
-  for (int d = 0; d < 4; ++d) b->nitems[d] = 0;
+  for (int d = 0; d < 7; ++d) b->nitems[d] = 0;
   hipError_t e = hipGetDevice(&b->device);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, b->device);
   if (e != hipSuccess) {

@@ -16,12 +16,15 @@ constexpr int kMaxK = 1024;       // wave vectors per structure-factor list
 constexpr int kSkChunks = 256;    // site chunks of the direct structure factor
 constexpr int kColChunks = 64;    // row chunks of the column marginals
 constexpr int kNVals = 40;        // lattice sums (see k_moments_partial)
+constexpr int kSampleRows = 16;   // rows per tile of the sampled step
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Byte offsets of the workspace regions.
 struct WorkLayout {
   size_t red_part, red_out, rowsum, colpart, marg, skpart, total;
+  size_t tw;              // twiddle tables of the three axes (2 (nx + ny + nz) doubles)
+  size_t rowpart, colbig; // partials of the sampled step (tiles of 256 x kSampleRows)
   // two k-list sets: [0] snapshot, [1] accumulator
   size_t kinfo[2], kv[2], slot_ax[2], slot_gen[2], sval[2];
   size_t skacc;
@@ -61,6 +64,8 @@ struct flb_lattice {
   std::vector<int32_t> klist[2];
   int64_t sk_count;
   int batch_refs;     // > 0 while a batch holds the lattice
+  int64_t sample_every;  // > 0: accumulate S(k) of the accumulator k-list every this many steps
+  bool sample_fused;     // the sampled step kernel produces the marginals
 };
 
 namespace flb {

@@ -74,6 +74,13 @@ __global__ void __launch_bounds__(256) k_step_plain(const T* __restrict__ g, T* 
   for (int i = 0; i < Q; ++i) h[i * P.n + s] = f[i];
 }
 
+// Flat step: block b covers sites b * 256 * RY ... (flat_tile).
+template <int D, typename T, int RY, bool NT>
+__global__ void __launch_bounds__(256) k_step_flat(const T* __restrict__ g, T* __restrict__ h,
+                                                   KParams<T> P, uint32_t step) {
+  flat_tile<D, T, RY, NT>(g, h, P, step, (int64_t)blockIdx.x * 256 * RY, threadIdx.x);
+}
+
 // Map a linear block index so that the blocks the dispatcher sends to one
 // XCD (round-robin over 8) cover one contiguous range of tiles, keeping the
 // shared halo lines of neighbouring tiles in one L2.
@@ -104,6 +111,118 @@ __device__ __forceinline__ void st_at(T* __restrict__ base, uint32_t byte_off, T
 // populations are loaded before any is collided, so that every wave keeps
 // RY * Q loads in flight; NT selects non-temporal stores (the new state is
 // not re-read within this launch).
+// Pre-collision populations of column x, row `row` (the pull gather).
+template <int D, typename T>
+__device__ __forceinline__ void load_row(const T* __restrict__ g, const KParams<T>& P, int64_t row,
+                                         uint32_t bx, uint32_t bxm, uint32_t bxp, T (&f)[2 * D + 1]) {
+  const int64_t n = P.n;
+  const uint32_t nx = (uint32_t)P.nx;
+  const int64_t base = row * (int64_t)nx;
+  f[0] = ld_at(g + base, bx);
+  f[1] = ld_at(g + n + base, bxm);
+  f[2] = ld_at(g + 2 * n + base, bxp);
+  if constexpr (D >= 2) {
+    uint32_t y, z;
+    if constexpr (D == 2) {
+      y = (uint32_t)row;
+      z = 0;
+    } else {
+      y = (uint32_t)row % (uint32_t)P.ny;
+      z = (uint32_t)row / (uint32_t)P.ny;
+    }
+    const uint32_t ny = (uint32_t)P.ny;
+    const uint32_t ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+    f[3] = ld_at(g + 3 * n + ((int64_t)ym + (int64_t)ny * z) * nx, bx);
+    f[4] = ld_at(g + 4 * n + ((int64_t)yp + (int64_t)ny * z) * nx, bx);
+    if constexpr (D >= 3) {
+      const uint32_t nz = (uint32_t)P.nz;
+      const uint32_t zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+      f[5] = ld_at(g + 5 * n + ((int64_t)y + (int64_t)ny * zm) * nx, bx);
+      f[6] = ld_at(g + 6 * n + ((int64_t)y + (int64_t)ny * zp) * nx, bx);
+    }
+  }
+}
+
+// Software-pipelined rows: the next row's loads are in flight while the
+// current row is collided and stored (RY rows per thread).
+template <int D, typename T, int RY, bool NT>
+__device__ __forceinline__ void rows_tile_pipe(const T* __restrict__ g, T* __restrict__ h,
+                                               const KParams<T>& P, uint32_t step, uint32_t x,
+                                               int64_t row0, int64_t nrows) {
+  constexpr int Q = 2 * D + 1;
+  const uint32_t nx = (uint32_t)P.nx;
+  if (x >= nx) return;
+  constexpr uint32_t S = sizeof(T);
+  const uint32_t bx = x * S;
+  const uint32_t bxm = (x == 0 ? nx - 1 : x - 1) * S, bxp = (x == nx - 1 ? 0 : x + 1) * S;
+  const int64_t rend = row0 + RY < nrows ? row0 + RY : nrows;
+  if (row0 >= rend) return;
+  T cur[Q];
+  load_row<D, T>(g, P, row0, bx, bxm, bxp, cur);
+  for (int64_t row = row0; row < rend; ++row) {
+    T nxt[Q];
+    const bool more = row + 1 < rend;
+    if (more) load_row<D, T>(g, P, row + 1, bx, bxm, bxp, nxt);
+    const int64_t base = row * (int64_t)nx;
+    Collide<D, T>::run(cur, P, (uint64_t)base + x, step);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) st_at<T, NT>(h + i * P.n + base, bx, cur[i]);
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
+    }
+  }
+}
+
+// Flat tile: RY blocks of 256 consecutive sites s0 + j * 256 + lane of the
+// row-major site order, so a lattice's sites fill every lane except in its
+// last tile.  Each lane derives (x, y, z) and its periodic neighbours
+// itself; all offsets are 32-bit byte offsets from the plane bases.
+template <int D, typename T, int RY, bool NT>
+__device__ __forceinline__ void flat_tile(const T* __restrict__ g, T* __restrict__ h,
+                                          const KParams<T>& P, uint32_t step, int64_t s0,
+                                          uint32_t lane) {
+  constexpr int Q = 2 * D + 1;
+  constexpr uint32_t S = sizeof(T);
+  const uint32_t nx = (uint32_t)P.nx, ny = (uint32_t)P.ny, nz = (uint32_t)P.nz;
+  const uint32_t n = (uint32_t)P.n;               // n * S < 2^32 (checked by the caller)
+  const uint32_t nxy = nx * ny;
+  T f[RY][Q];
+  uint32_t sj[RY];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) {
+    const uint32_t s = (uint32_t)s0 + (uint32_t)j * 256u + lane;
+    sj[j] = s;
+    if (s < n) {
+      const uint32_t x = s % nx, rest = s / nx;
+      const uint32_t sxm = x == 0 ? s + nx - 1 : s - 1, sxp = x == nx - 1 ? s + 1 - nx : s + 1;
+      f[j][0] = ld_at(g, s * S);
+      f[j][1] = ld_at(g + n, sxm * S);
+      f[j][2] = ld_at(g + 2 * (int64_t)n, sxp * S);
+      if constexpr (D >= 2) {
+        const uint32_t y = D == 2 ? rest : rest % ny;
+        const uint32_t sym = y == 0 ? s + nxy - nx : s - nx, syp = y == ny - 1 ? s + nx - nxy : s + nx;
+        f[j][3] = ld_at(g + 3 * (int64_t)n, sym * S);
+        f[j][4] = ld_at(g + 4 * (int64_t)n, syp * S);
+        if constexpr (D >= 3) {
+          const uint32_t z = rest / ny;
+          const uint32_t szm = z == 0 ? s + n - nxy : s - nxy, szp = z == nz - 1 ? s + nxy - n : s + nxy;
+          f[j][5] = ld_at(g + 5 * (int64_t)n, szm * S);
+          f[j][6] = ld_at(g + 6 * (int64_t)n, szp * S);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < RY; ++j) {
+    if (sj[j] < n) {
+      Collide<D, T>::run(f[j], P, (uint64_t)sj[j], step);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) st_at<T, NT>(h + i * (int64_t)n, sj[j] * S, f[j][i]);
+    }
+  }
+}
+
 // Column x of rows row0 .. row0 + RY - 1 (row0 is uniform over a wave).
 template <int D, typename T, int RY, bool NT>
 __device__ __forceinline__ void rows_tile(const T* __restrict__ g, T* __restrict__ h,
@@ -161,14 +280,18 @@ __device__ __forceinline__ void rows_tile(const T* __restrict__ g, T* __restrict
   }
 }
 
-template <int D, typename T, int RY, bool NT>
+template <int D, typename T, int RY, bool NT, bool PIPE = false>
 __global__ void __launch_bounds__(1024) k_step_rows(const T* __restrict__ g, T* __restrict__ h,
                                                     KParams<T> P, uint32_t step, int64_t tiles_x,
                                                     int64_t nrows, int remap) {
   const int64_t G = (int64_t)gridDim.x;
   const int64_t tile = remap ? xcd_tile(blockIdx.x, G) : (int64_t)blockIdx.x;
   const int64_t tx = tile % tiles_x, tr = tile / tiles_x;
-  rows_tile<D, T, RY, NT>(g, h, P, step, (uint32_t)(tx * blockDim.x) + threadIdx.x, tr * RY, nrows);
+  const uint32_t x = (uint32_t)(tx * blockDim.x) + threadIdx.x;
+  if constexpr (PIPE)
+    rows_tile_pipe<D, T, RY, NT>(g, h, P, step, x, tr * RY, nrows);
+  else
+    rows_tile<D, T, RY, NT>(g, h, P, step, x, tr * RY, nrows);
 }
 
 // ---------------------------------------------------------------------------

@@ -156,22 +156,64 @@ __global__ void __launch_bounds__(256) k_col_partial(const T* __restrict__ g, in
   colpart[c * nx + x] = acc;
 }
 
-// Axis marginals from the partials: mx[x] = sum_c colpart[c][x] and
-// my[y] = sum_z rowsum[y + ny z] (one thread each, short fixed loops).
-__global__ void k_marginals_xy(const double* __restrict__ colpart, int64_t nchunk,
-                               const double* __restrict__ rowsum, int64_t nx, int64_t ny,
-                               int64_t nz, double* __restrict__ mx, double* __restrict__ my) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < nx) {
-    double acc = 0;
-    for (int64_t c = 0; c < nchunk; ++c) acc += colpart[c * nx + t];
-    mx[t] = acc;
-  } else if (t < nx + ny) {
-    const int64_t y = t - nx;
-    double acc = 0;
-    for (int64_t z = 0; z < nz; ++z) acc += rowsum[y + ny * z];
-    my[y] = acc;
-  }
+// Axis marginal along x from column partials: mx[x] = sum_c colpart[c][x].
+// A block covers 64 columns; its 4 waves sum interleaved chunk subsets and
+// are combined in wave order (deterministic).
+__global__ void __launch_bounds__(256) k_marginal_x(const double* __restrict__ colpart,
+                                                    int64_t nchunk, int64_t nx,
+                                                    double* __restrict__ mx) {
+  __shared__ double part[4][64];
+  const int lx = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int64_t x = (int64_t)blockIdx.x * 64 + lx;
+  double acc = 0;
+  if (x < nx)
+    for (int64_t c = grp; c < nchunk; c += 4) acc += colpart[c * nx + x];
+  part[grp][lx] = acc;
+  __syncthreads();
+  if (grp == 0 && x < nx) mx[x] = ((part[0][lx] + part[1][lx]) + part[2][lx]) + part[3][lx];
+}
+
+// my[y] = sum_z rowsum[y + ny z] (one thread per y).
+__global__ void k_marginal_y(const double* __restrict__ rowsum, int64_t ny, int64_t nz,
+                             double* __restrict__ my) {
+  const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= ny) return;
+  double acc = 0;
+  for (int64_t z = 0; z < nz; ++z) acc += rowsum[y + ny * z];
+  my[y] = acc;
+}
+
+// out[g][x] = sum of in[c][x] over the chunks c of group g (groups of
+// consecutive chunks, in order): shrinks many column partials to ngroup.
+__global__ void k_colpart_reduce(const double* __restrict__ in, int64_t nchunk, int64_t nx,
+                                 int64_t ngroup, double* __restrict__ out) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t g = blockIdx.y;
+  if (x >= nx) return;
+  const int64_t c0 = g * nchunk / ngroup, c1 = (g + 1) * nchunk / ngroup;
+  double acc = 0;
+  for (int64_t c = c0; c < c1; ++c) acc += in[c * nx + x];
+  out[g * nx + x] = acc;
+}
+
+// rowsum[row] = sum over x tiles of rowpart[t][row].
+__global__ void k_rowpart_reduce(const double* __restrict__ rowpart, int64_t ntx, int64_t nrows,
+                                 double* __restrict__ rowsum) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= nrows) return;
+  double acc = 0;
+  for (int64_t t = 0; t < ntx; ++t) acc += rowpart[t * nrows + row];
+  rowsum[row] = acc;
+}
+
+// Twiddles of one axis: tw[2p] = cos(2 pi p / L), tw[2p + 1] = sin(2 pi p / L).
+__global__ void k_twiddle(double* __restrict__ tw, int64_t L) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= L) return;
+  double s, c;
+  sincospi(2.0 * (double)p / (double)L, &s, &c);
+  tw[2 * p] = c;
+  tw[2 * p + 1] = s;
 }
 
 // mz[z] = sum_y rowsum[y + ny z]: one block per z (3-D lattices only).
@@ -185,7 +227,8 @@ __global__ void __launch_bounds__(256) k_marginal_z(const double* __restrict__ r
   if (threadIdx.x == 0) mz[z] = acc;
 }
 
-// Axis structure factor from a marginal: one block per wave vector.
+// Axis structure factor from a marginal: one block per wave vector; the
+// twiddles come from a table of the axis (k_twiddle).
 // kinfo[j] = (axis, k mod L_axis); axis < 0 marks a k = 0 entry.
 // S = |sum_x (m(x) - mean) e^{-2 pi i k x / L}|^2 / N; k = 0 gives M^2 / N.
 __global__ void __launch_bounds__(256) k_sk_axis(const double* __restrict__ mx,
@@ -194,12 +237,16 @@ __global__ void __launch_bounds__(256) k_sk_axis(const double* __restrict__ mx,
                                                  int64_t ny, int64_t nz,
                                                  const int64_t* __restrict__ kinfo,
                                                  const int32_t* __restrict__ slot,
+                                                 const double* __restrict__ twx,
+                                                 const double* __restrict__ twy,
+                                                 const double* __restrict__ twz,
                                                  double* __restrict__ sval) {
   __shared__ double lds[4];
   const int j = blockIdx.x;
   const int64_t axis = kinfo[2 * j], k = kinfo[2 * j + 1];
   const double N = (double)(nx * ny * nz);
   const double* m = axis == 1 ? my : (axis == 2 ? mz : mx);
+  const double* tw = axis == 1 ? twy : (axis == 2 ? twz : twx);
   const int64_t L = axis == 1 ? ny : (axis == 2 ? nz : nx);
   // mass from the chosen marginal
   double tot = 0;
@@ -216,8 +263,7 @@ __global__ void __launch_bounds__(256) k_sk_axis(const double* __restrict__ mx,
   double re = 0, im = 0;
   for (int64_t x = threadIdx.x; x < L; x += blockDim.x) {
     const int64_t p = (k * x) % L;  // integer phase
-    double s, c;
-    sincospi(2.0 * (double)p / (double)L, &s, &c);
+    const double c = tw[2 * p], s = tw[2 * p + 1];
     const double v = m[x] - mean;
     re += v * c;
     im -= v * s;
@@ -291,6 +337,90 @@ __global__ void k_sk_accumulate(const double* __restrict__ sval, double* __restr
 __global__ void k_fill_zero(double* __restrict__ p, int64_t n) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j < n) p[j] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Sampled step: the step of k_step_rows (same arithmetic, bit-identical
+// result) for a tile of 256 columns x RY rows, which also accumulates the
+// FP64 density of the pre-collision state into
+//   rowpart[tx][row] = sum over the tile's columns of rho(x, row)
+//   colpart[tr][x]   = sum over the tile's rows of rho(x, row)
+// (LDS reductions in a fixed order), the inputs of the axis marginals.
+template <int D, typename T, int RY>
+__global__ void __launch_bounds__(256) k_step_rows_sk(const T* __restrict__ g, T* __restrict__ h,
+                                                      KParams<T> P, uint32_t step, int64_t tiles_x,
+                                                      int64_t nrows, double* __restrict__ rowpart,
+                                                      double* __restrict__ colpart) {
+  constexpr int Q = 2 * D + 1;
+  constexpr int NP = 256 / RY;  // row partials per row in the first pass
+  __shared__ double red[RY][256];
+  __shared__ double red2[RY][NP];
+  const int64_t tile = blockIdx.x;
+  const int64_t tx = tile % tiles_x, tr = tile / tiles_x;
+  const uint32_t nx = (uint32_t)P.nx;
+  const int tid = threadIdx.x;
+  const uint32_t x = (uint32_t)(tx * 256) + tid;
+  const bool valid = x < nx;
+  const int64_t row0 = tr * RY;
+  double col = 0;
+#pragma unroll
+  for (int r = 0; r < RY; ++r) red[r][tid] = 0.0;
+  if (valid) {
+    const int64_t n = P.n;
+    constexpr uint32_t S = sizeof(T);
+    const uint32_t bx = x * S;
+    const uint32_t bxm = (x == 0 ? nx - 1 : x - 1) * S, bxp = (x == nx - 1 ? 0 : x + 1) * S;
+    for (int r = 0; r < RY; ++r) {
+      const int64_t row = row0 + r;
+      if (row >= nrows) break;
+      const int64_t base = row * (int64_t)nx;
+      T f[Q];
+      f[0] = ld_at(g + base, bx);
+      f[1] = ld_at(g + n + base, bxm);
+      f[2] = ld_at(g + 2 * n + base, bxp);
+      if constexpr (D >= 2) {
+        uint32_t y, z;
+        if constexpr (D == 2) {
+          y = (uint32_t)row;
+          z = 0;
+        } else {
+          y = (uint32_t)row % (uint32_t)P.ny;
+          z = (uint32_t)row / (uint32_t)P.ny;
+        }
+        const uint32_t ny = (uint32_t)P.ny;
+        const uint32_t ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+        f[3] = ld_at(g + 3 * n + ((int64_t)ym + (int64_t)ny * z) * nx, bx);
+        f[4] = ld_at(g + 4 * n + ((int64_t)yp + (int64_t)ny * z) * nx, bx);
+        if constexpr (D >= 3) {
+          const uint32_t nz = (uint32_t)P.nz;
+          const uint32_t zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+          f[5] = ld_at(g + 5 * n + ((int64_t)y + (int64_t)ny * zm) * nx, bx);
+          f[6] = ld_at(g + 6 * n + ((int64_t)y + (int64_t)ny * zp) * nx, bx);
+        }
+      }
+      const double rho = density_sum(f);
+      red[r][tid] = rho;
+      col += rho;
+      Collide<D, T>::run(f, P, (uint64_t)base + x, step);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) st_at<T, false>(h + i * n + base, bx, f[i]);
+    }
+    colpart[tr * (int64_t)nx + x] = col;
+  }
+  __syncthreads();
+  {  // first pass: thread (r, part) sums RY consecutive columns of row r
+    const int r = tid / NP, part = tid % NP;
+    double acc = 0;
+#pragma unroll
+    for (int j = 0; j < RY; ++j) acc += red[r][part * RY + j];
+    red2[r][part] = acc;
+  }
+  __syncthreads();
+  if (tid < RY && row0 + tid < nrows) {
+    double acc = 0;
+    for (int p2 = 0; p2 < NP; ++p2) acc += red2[tid][p2];
+    rowpart[tx * nrows + row0 + tid] = acc;
+  }
 }
 
 }  // namespace flb

@@ -18,14 +18,14 @@ FLB_OK, FLB_EINVAL, FLB_ENOMEM, FLB_EDEVICE, FLB_ESTATE, FLB_ENONFINITE = 0, -1,
 MODELS = {"D1Q3": 1, "D2Q5": 2, "D3Q7": 3, 1: 1, 2: 2, 3: 3}
 NOISE = {"local": 0, "global": 1, "off": 2}
 LAWS = {"gauss": 0, "uniform": 1}
-KERNELS = {"auto": 0, "plain": 1, "rows": 2}
+KERNELS = {"auto": 0, "plain": 1, "rows": 2, "flat": 3}
 SK_SNAPSHOT, SK_SAMPLE, SK_READ, SK_RESET = 0, 1, 2, 3
 
 # exported symbols, in the order include/flb.h declares them
 EXPORTS = (
     "flb_version", "flb_last_error", "flb_lattice_constants", "flb_required_bytes",
     "flb_create", "flb_set_populations", "flb_get_populations", "flb_step",
-    "flb_get_step", "flb_moments", "flb_structure_factor", "flb_sync", "flb_destroy",
+    "flb_get_step", "flb_moments", "flb_structure_factor", "flb_set_sampling", "flb_sync", "flb_destroy",
     "flb_noise_sample", "flb_batch_create", "flb_batch_admit", "flb_batch_retire",
     "flb_batch_step", "flb_batch_size", "flb_batch_sync", "flb_batch_destroy",
 )
@@ -45,7 +45,7 @@ class Params(ctypes.Structure):
         ("noise", ctypes.c_int32), ("noise_law", ctypes.c_int32),
         ("layout", ctypes.c_int32), ("kernel", ctypes.c_int32),
         ("tile_x", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
-        ("nt_store", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("nt_store", ctypes.c_int32), ("pipeline", ctypes.c_int32),
     ]
 
 
@@ -63,7 +63,7 @@ class BatchOpts(ctypes.Structure):
     _fields_ = [
         ("chunk", ctypes.c_int32), ("use_graph", ctypes.c_int32),
         ("lds_max_bytes", ctypes.c_int32), ("workers", ctypes.c_int32),
-        ("item_rows", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("item_rows", ctypes.c_int32), ("tiling", ctypes.c_int32),
         ("hip_stream", ctypes.c_void_p),
     ]
 
@@ -95,6 +95,7 @@ def load(path=LIB_PATH):
         "flb_get_step": ([vp, ctypes.POINTER(i64)], ctypes.c_int),
         "flb_moments": ([vp, ctypes.POINTER(Moments)], ctypes.c_int),
         "flb_structure_factor": ([vp, vp, i32, i32, dp], ctypes.c_int),
+        "flb_set_sampling": ([vp, i64, vp, i32], ctypes.c_int),
         "flb_sync": ([vp], ctypes.c_int),
         "flb_destroy": ([vp], ctypes.c_int),
         "flb_noise_sample": ([i32, i32, i32, u64, i64, i64, i64, vp, vp, vp], ctypes.c_int),
@@ -139,7 +140,8 @@ def constants(model, theta=0.0):
 
 
 def make_params(model, dims, precision=4, theta=0.0, omega=1.0, omega_n=0.0, omega_s=0.0,
-                seed=0, noise="local", law="gauss", kernel="auto", tile_x=0, tile_rows=0, nt_store=0):
+                seed=0, noise="local", law="gauss", kernel="auto", tile_x=0, tile_rows=0, nt_store=0,
+                pipeline=0):
     d = MODELS[model]
     dims = tuple(int(x) for x in dims) + (1,) * (3 - len(dims))
     p = Params()
@@ -157,6 +159,7 @@ def make_params(model, dims, precision=4, theta=0.0, omega=1.0, omega_n=0.0, ome
     p.tile_x = int(tile_x)
     p.tile_rows = int(tile_rows)
     p.nt_store = int(nt_store)
+    p.pipeline = int(pipeline)
     return p
 
 
@@ -282,6 +285,14 @@ class Lattice:
             return out
         return None
 
+    def set_sampling(self, every, kvecs=None):
+        """Accumulate S(k) of kvecs while stepping, every `every` steps."""
+        if every and kvecs is not None:
+            kv = self._kvec(kvecs)
+            check(load().flb_set_sampling(self.handle, int(every), _ptr(kv), len(kv)))
+        else:
+            check(load().flb_set_sampling(self.handle, 0, None, 0))
+
     def close(self):
         if getattr(self, "handle", None):
             check(load().flb_destroy(self.handle))
@@ -300,10 +311,12 @@ class Batch:
     LDS for small D1Q3 lattices, chunks captured in a HIP graph.  Results
     are bit-identical to stepping each member alone."""
 
-    def __init__(self, chunk=16, use_graph=True, lds_max_bytes=0, workers=0, item_rows=0, stream=None):
+    def __init__(self, chunk=16, use_graph=True, lds_max_bytes=0, workers=0, item_rows=0, tiling=0,
+                 stream=None):
         o = BatchOpts()
         o.chunk, o.use_graph, o.lds_max_bytes, o.workers = int(chunk), int(bool(use_graph)), int(lds_max_bytes), int(workers)
         o.item_rows = int(item_rows)
+        o.tiling = int(tiling)
         o.hip_stream = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
         h = ctypes.c_void_p()
         check(load().flb_batch_create(ctypes.byref(o), ctypes.byref(h)))

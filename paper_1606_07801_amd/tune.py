@@ -22,8 +22,13 @@ DEFAULTS = {1: dict(kernel="rows", tile_x=256, tile_rows=1, nt_store=0),
             2: dict(kernel="rows", tile_x=256, tile_rows=4, nt_store=0),
             3: dict(kernel="rows", tile_x=256, tile_rows=4, nt_store=0)}
 
-CANDIDATES = [("plain", 0, 0, 0)] + [("rows", tx, ry, nt) for tx in (64, 128, 256, 512, 1024)
-                                     for ry in (1, 2, 4, 8, 16) for nt in (0, 1)]
+CANDIDATES = ([("plain", 0, 0, 0, 0)] +
+              [("flat", 0, ry, nt, 0) for ry in (1, 2, 4, 8) for nt in (0, 1)] +
+              [("rows", tx, ry, nt, 0) for tx in (64, 128, 256, 512, 1024) for ry in (1, 2, 4, 8, 16)
+               for nt in (0, 1)] +
+              [("rows", tx, ry, nt, 1) for tx in (128, 256, 512) for ry in (2, 4, 8, 16) for nt in (0, 1)])
+QUICK = ([("plain", 0, 0, 0, 0)] + [("flat", 0, ry, nt, 0) for ry in (1, 2, 4) for nt in (0, 1)] +
+         [("rows", tx, ry, 1, 0) for tx in (256, 512) for ry in (1, 2, 4)])
 
 
 def size_class(dims):
@@ -49,12 +54,15 @@ def best_config(d, precision, dims):
     ent = _load().get(_key(d, precision, dims))
     if ent:
         return dict(kernel=ent["kernel"], tile_x=ent["tile_x"], tile_rows=ent["tile_rows"],
-                    nt_store=ent.get("nt_store", 0))
+                    nt_store=ent.get("nt_store", 0), pipeline=ent.get("pipeline", 0))
     return dict(DEFAULTS[d])
 
 
 def tune(d, precision, dims, steps=100, candidates=None, write=True, verbose=True):
-    """Time every candidate on `dims` and cache the fastest bit-identical one."""
+    """Time every candidate on `dims` and cache the fastest bit-identical one
+    (candidates "quick" = a short list of the shapes that have won before)."""
+    if candidates == "quick":
+        candidates = QUICK
     import torch
     from . import flb, inputs
 
@@ -62,11 +70,13 @@ def tune(d, precision, dims, steps=100, candidates=None, write=True, verbose=Tru
     f0 = inputs.poisson_counts(dims, 10.0 * w, seed=0).astype(np.float32 if precision == 4 else np.float64)
     ref = None
     results = []
-    for kern, tx, ry, nt in (candidates or CANDIDATES):
+    for cand in (candidates or CANDIDATES):
+        kern, tx, ry, nt = cand[:4]
+        pp = cand[4] if len(cand) > 4 else 0
         if d == 1 and ry > 1:
             continue
         L = flb.Lattice(d, dims, precision=precision, omega=1.0, seed=0, kernel=kern, tile_x=tx,
-                        tile_rows=ry, nt_store=nt)
+                        tile_rows=ry, nt_store=nt, pipeline=pp)
         L.set_populations(f0)
         L.step(3)
         state = L.get_populations()
@@ -82,9 +92,10 @@ def tune(d, precision, dims, steps=100, candidates=None, write=True, verbose=Tru
         e1.synchronize()
         ms = e0.elapsed_time(e1) / steps
         L.close()
-        results.append(dict(kernel=kern, tile_x=tx, tile_rows=ry, nt_store=nt, ms=ms, identical=bool(same)))
+        results.append(dict(kernel=kern, tile_x=tx, tile_rows=ry, nt_store=nt, pipeline=pp, ms=ms,
+                            identical=bool(same)))
         if verbose:
-            print(f"[tune] D{d} fp{8 * precision} {dims} {kern} {tx}x{ry} nt={nt}: {ms * 1e3:.1f} us/step"
+            print(f"[tune] D{d} fp{8 * precision} {dims} {kern} {tx}x{ry} nt={nt} pipe={pp}: {ms * 1e3:.1f} us/step"
                   f"{'' if same else '  (NOT bit-identical: rejected)'}", flush=True)
     ok = [r for r in results if r["identical"]]
     best = min(ok, key=lambda r: r["ms"])

@@ -46,12 +46,12 @@ def _alone(specs, precision, nsteps, t0):
 
 
 @pytest.mark.parametrize("precision", [4, 8])
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_batch_bit_identical_to_alone(precision, use_graph):
+@pytest.mark.parametrize("use_graph,tiling", [(True, 0), (False, 0), (True, 1)])
+def test_batch_bit_identical_to_alone(precision, use_graph, tiling):
     specs = _specs()
     nsteps, t0 = 37, 5           # 2 chunks of 16 + a remainder of 5
     ref = _alone(specs, precision, nsteps, t0)
-    B = flb.Batch(chunk=16, use_graph=use_graph)
+    B = flb.Batch(chunk=16, use_graph=use_graph, tiling=tiling)
     lats = []
     for spec in specs:
         f0, kw = _member(spec, precision)

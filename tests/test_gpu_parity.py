@@ -81,9 +81,12 @@ def test_kernel_variants_bit_identical(d, precision):
     dims = SIZES[d]
     f0 = poisson_state(d, dims, 10.0, seed=3).astype(np.float32 if precision == 4 else np.float64)
     outs = []
-    for kern, tx, ry, nt in [("plain", 0, 0, 0), ("rows", 256, 4, 0), ("rows", 64, 1, 1), ("rows", 1024, 16, 0),
-                             ("rows", 128, 8, 1), ("rows", 512, 2, 0), ("rows", 256, 16, 1)]:
-        L = gpu_lattice(d, dims, precision, omega=1.2, seed=5, kernel=kern, tile_x=tx, tile_rows=ry, nt_store=nt)
+    for kern, tx, ry, nt, pp in [("plain", 0, 0, 0, 0), ("rows", 256, 4, 0, 0), ("rows", 64, 1, 1, 0),
+                                 ("rows", 1024, 16, 0, 0), ("rows", 128, 8, 1, 0), ("rows", 512, 2, 0, 0),
+                                 ("rows", 256, 16, 1, 0), ("rows", 256, 4, 1, 1), ("rows", 128, 16, 0, 1),
+                                 ("flat", 0, 1, 0, 0), ("flat", 0, 2, 1, 0), ("flat", 0, 8, 1, 0)]:
+        L = gpu_lattice(d, dims, precision, omega=1.2, seed=5, kernel=kern, tile_x=tx, tile_rows=ry, nt_store=nt,
+                        pipeline=pp)
         L.set_populations(f0)
         L.step(12)
         outs.append(L.get_populations())

@@ -194,3 +194,34 @@ def test_flat_structure_factor_gpu_low_density_local():
     print(f"[flat] rho=0.1 local: <rho+> {pos:.4f} rho_eq {rho_eq:.4f} max |z| {np.abs(z).max():.2f}")
     assert np.abs(z).max() < 5 and np.mean(z ** 2) < 2.5
     assert pos > 1.3 * rho_eq
+
+
+@pytest.mark.parametrize("precision", [4, 8])
+@pytest.mark.parametrize("d,dims", [(1, (300,)), (2, (300, 70)), (3, (40, 33, 17))])
+def test_sampling_while_stepping(d, dims, precision):
+    # the sampled step leaves the trajectory bit-identical, and its S(k)
+    # accumulation equals sampling the same states by a separate pass
+    f0 = poisson_state(d, dims, 10.0, seed=12)
+    ks = [tuple([0] * d)] + [tuple(k if a == ax else 0 for a in range(d)) for ax in range(d)
+                             for k in (1, 3, dims[ax] // 2)]
+    A = gpu_lattice(d, dims, precision, omega=1.2, seed=4)
+    A.set_populations(f0)
+    A.set_sampling(3, ks)
+    A.step(20)
+    Sa = A.structure_factor(None, mode="read")[:len(ks)]
+    B = gpu_lattice(d, dims, precision, omega=1.2, seed=4)
+    B.set_populations(f0)
+    B.structure_factor(ks, mode="reset")
+    for t in range(20):
+        if t % 3 == 0:
+            B.structure_factor(ks, mode="sample")
+        B.step(1)
+    Sb = B.structure_factor(None, mode="read")[:len(ks)]
+    assert np.array_equal(A.get_populations(), B.get_populations())
+    assert np.abs(Sa - Sb).max() <= 1e-12 * np.abs(Sb).max()
+    # a general wave vector takes the separate pass
+    A.set_sampling(2, [tuple(range(1, d + 1))])
+    A.step(4)
+    A.set_sampling(0)
+    A.close()
+    B.close()
