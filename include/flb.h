@@ -184,6 +184,17 @@ int flb_structure_factor(flb_lattice* h, const int32_t* kvec, int32_t nk, int32_
  * populations).  every = 0 stops sampling (kvec may be NULL). */
 int flb_set_sampling(flb_lattice* h, int64_t every, const int32_t* kvec, int32_t nk);
 
+/* Accumulate the lattice sums (as flb_moments) of the state before every
+ * step t with t % every == 0 while stepping, on the device (no
+ * synchronisation); every = 0 stops.  Starting resets the accumulator.  These
+ * are the space-time sums of Sec. IV (means of f_i and of f_i f_j, eq. dijexp). */
+int flb_set_moment_sampling(flb_lattice* h, int64_t every);
+
+/* The accumulated sums (every field summed over the samples; step, nsite,
+ * mass0 and rho_eq as for flb_moments) and the number of samples.
+ * Synchronises the stream. */
+int flb_sampled_moments(flb_lattice* h, flb_moments_t* sum, int64_t* nsamples);
+
 /* Block until the handle's stream has finished. */
 int flb_sync(flb_lattice* h);
 

@@ -158,6 +158,7 @@ WorkLayout work_layout(const flb_params& p) {
     L.sval[s] = take(sizeof(double) * kMaxK);
   }
   L.skacc = take(sizeof(double) * kMaxK);
+  L.momacc = take(sizeof(double) * kNVals);
   L.total = o;
   return L;
 }
@@ -553,6 +554,8 @@ int flb_create(const flb_params* p, void* d_pop, size_t pop_bytes, void* d_work,
   }
   h->sample_every = 0;
   h->sample_fused = false;
+  h->mom_every = 0;
+  h->mom_count = 0;
   if (h->d >= 2) {  // twiddle tables of the axis structure factor
     double* tw = (double*)(h->work + h->wl.tw);
     const int64_t L3[3] = {p->n[0], p->n[1], p->n[2]};
@@ -626,6 +629,11 @@ int flb_step(flb_lattice* h, int64_t nsteps) {
   for (int64_t k = 0; k < nsteps; ++k) {
     const int nxt = 1 - h->cur;
     const uint32_t t32 = (uint32_t)(h->step & 0xFFFFFFFF);
+    if (h->mom_every > 0 && h->step % h->mom_every == 0) {  // lattice sums of the state before this step
+      launch_moments(h);
+      k_add<<<1, 64, 0, h->stream>>>((const double*)(h->work + h->wl.red_out), (double*)(h->work + h->wl.momacc), kNV);
+      h->mom_count += 1;
+    }
     const bool sample = h->sample_every > 0 && h->step % h->sample_every == 0;
     if (sample && h->sample_fused) {
       launch_step_sampled(h, lat_buffer(h, h->cur), lat_buffer(h, nxt), t32);
@@ -734,6 +742,43 @@ int flb_set_sampling(flb_lattice* h, int64_t every, const int32_t* kvec, int32_t
   if (rc) return rc;
   h->sample_every = every;
   h->sample_fused = h->d >= 2 && h->ngen[1] == 0;
+  return FLB_OK;
+}
+
+int flb_set_moment_sampling(flb_lattice* h, int64_t every) {
+  if (!h) return fail(FLB_EINVAL, "NULL handle");
+  if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
+  if (every < 0) return fail(FLB_EINVAL, "every must be >= 0");
+  DeviceGuard g(h->device);
+  if (every > 0) {
+    k_fill_zero<<<1, 64, 0, h->stream>>>((double*)(h->work + h->wl.momacc), kNV);
+    HIP_TRY(hipGetLastError());
+    h->mom_count = 0;
+  }
+  h->mom_every = every;
+  return FLB_OK;
+}
+
+int flb_sampled_moments(flb_lattice* h, flb_moments_t* sum, int64_t* nsamples) {
+  if (!h || !sum || !nsamples) return fail(FLB_EINVAL, "NULL argument");
+  if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
+  DeviceGuard g(h->device);
+  HIP_TRY(hipMemcpyAsync(h->stage->red, h->work + h->wl.momacc, sizeof(double) * kNV, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  const double* r = h->stage->red;
+  std::memset(sum, 0, sizeof *sum);
+  sum->step = h->step;
+  sum->nsite = h->n;
+  sum->mass = r[0];
+  sum->mass0 = h->mass0;
+  sum->rho_eq = h->rho_eq;
+  for (int i = 0; i < 7; ++i) sum->sum_f[i] = r[1 + i];
+  for (int i = 0; i < 28; ++i) sum->sum_ff[i] = r[8 + i];
+  sum->sum_rho2 = r[36];
+  sum->sum_rho_pos = r[37];
+  sum->n_negative = (int64_t)r[38];
+  sum->nonfinite = (int64_t)r[39];
+  *nsamples = h->mom_count;
   return FLB_OK;
 }
 

@@ -25,6 +25,7 @@ struct WorkLayout {
   size_t red_part, red_out, rowsum, colpart, marg, skpart, total;
   size_t tw;              // twiddle tables of the three axes (2 (nx + ny + nz) doubles)
   size_t rowpart, colbig; // partials of the sampled step (tiles of 256 x kSampleRows)
+  size_t momacc;          // accumulated lattice sums of sampled states (kNVals doubles)
   // two k-list sets: [0] snapshot, [1] accumulator
   size_t kinfo[2], kv[2], slot_ax[2], slot_gen[2], sval[2];
   size_t skacc;
@@ -66,6 +67,8 @@ struct flb_lattice {
   int batch_refs;     // > 0 while a batch holds the lattice
   int64_t sample_every;  // > 0: accumulate S(k) of the accumulator k-list every this many steps
   bool sample_fused;     // the sampled step kernel produces the marginals
+  int64_t mom_every;     // > 0: accumulate the lattice sums every this many steps
+  int64_t mom_count;     // samples in the lattice-sum accumulator
 };
 
 namespace flb {

@@ -329,6 +329,11 @@ __global__ void k_sk_direct_final(const double* __restrict__ partial, int64_t nc
   }
 }
 
+__global__ void k_add(const double* __restrict__ v, double* __restrict__ acc, int n) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) acc[j] += v[j];
+}
+
 __global__ void k_sk_accumulate(const double* __restrict__ sval, double* __restrict__ acc, int nk) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < nk) acc[j] += sval[j];

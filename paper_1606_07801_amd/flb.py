@@ -25,7 +25,8 @@ SK_SNAPSHOT, SK_SAMPLE, SK_READ, SK_RESET = 0, 1, 2, 3
 EXPORTS = (
     "flb_version", "flb_last_error", "flb_lattice_constants", "flb_required_bytes",
     "flb_create", "flb_set_populations", "flb_get_populations", "flb_step",
-    "flb_get_step", "flb_moments", "flb_structure_factor", "flb_set_sampling", "flb_sync", "flb_destroy",
+    "flb_get_step", "flb_moments", "flb_structure_factor", "flb_set_sampling",
+    "flb_set_moment_sampling", "flb_sampled_moments", "flb_sync", "flb_destroy",
     "flb_noise_sample", "flb_batch_create", "flb_batch_admit", "flb_batch_retire",
     "flb_batch_step", "flb_batch_size", "flb_batch_sync", "flb_batch_destroy",
 )
@@ -79,6 +80,12 @@ def load(path=LIB_PATH):
     if not os.path.exists(path):
         raise FileNotFoundError(
             f"{path} is not built; run `python -m paper_1606_07801_amd.build` first")
+    # torch (which allocates the device buffers) ships its own HIP runtime
+    # under the same soname as the system one.  Loading torch first makes
+    # the library bind to that runtime, so the process holds one HIP runtime;
+    # with the system runtime loaded first, device queries in the library
+    # can fail while torch still sees the GPU.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, i32, i64, u64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p
     sig = {
@@ -96,6 +103,8 @@ def load(path=LIB_PATH):
         "flb_moments": ([vp, ctypes.POINTER(Moments)], ctypes.c_int),
         "flb_structure_factor": ([vp, vp, i32, i32, dp], ctypes.c_int),
         "flb_set_sampling": ([vp, i64, vp, i32], ctypes.c_int),
+        "flb_set_moment_sampling": ([vp, i64], ctypes.c_int),
+        "flb_sampled_moments": ([vp, ctypes.POINTER(Moments), ctypes.POINTER(i64)], ctypes.c_int),
         "flb_sync": ([vp], ctypes.c_int),
         "flb_destroy": ([vp], ctypes.c_int),
         "flb_noise_sample": ([i32, i32, i32, u64, i64, i64, i64, vp, vp, vp], ctypes.c_int),
@@ -248,6 +257,20 @@ class Lattice:
     def moments(self):
         m = Moments()
         check(load().flb_moments(self.handle, ctypes.byref(m)))
+        return self._moments_dict(m)
+
+    def set_moment_sampling(self, every):
+        """Accumulate the lattice sums on the device every `every` steps."""
+        check(load().flb_set_moment_sampling(self.handle, int(every)))
+
+    def sampled_moments(self):
+        """(sums over the samples, number of samples)."""
+        m = Moments()
+        n = ctypes.c_int64()
+        check(load().flb_sampled_moments(self.handle, ctypes.byref(m), ctypes.byref(n)))
+        return self._moments_dict(m), n.value
+
+    def _moments_dict(self, m):
         Q = self.Q
         ff = np.zeros((Q, Q))
         k = 0
