@@ -195,6 +195,38 @@ int flb_set_moment_sampling(flb_lattice* h, int64_t every);
  * Synchronises the stream. */
 int flb_sampled_moments(flb_lattice* h, flb_moments_t* sum, int64_t* nsamples);
 
+/* ---- Population correlators (Sec. IV: Fourier test and equilibrium dynamics)
+ *
+ * With the paper's sign, f_i(k, t) = sum_x exp(+2 pi i k.x / L) f_i(x, t),
+ * k.x / L = sum_a k_a x_a / L_a, and rho(k) = sum_i f_i(k).  While stepping,
+ * at every step t with t % every == 0 (state before that step's collision)
+ * the library adds
+ *   S_ij(k)  += f_i(k, t) conj(f_j(k, t))         = f_i(k) f_j(-k), eqs. fkfk / FourierTest
+ *   C(k, l)  += rho(k, t_s) conj(rho(k, t_{s+l}))  l = 0 .. nlag-1, eq. TimeCorrEqn
+ * where t_s is the s-th sample since the last flb_set_correlation; the lag-l
+ * sum has (nsamples - l) terms (none while nsamples <= l).  FP64 sums in a
+ * fixed order.
+ *
+ * flb_set_correlation: kvec is nk x 3 int32 wave numbers (host memory,
+ * components beyond the lattice's dimension ignored, any integer, taken
+ * modulo the box), 1 <= nk <= 1024, 1 <= nlag <= 65536, nk * nlag <= 2^20.
+ * The library allocates the buffers (device memory, about
+ * 16 (nk (Q (Q + 1 + 256)) + 2 nk nlag) bytes) on this call, replaces any
+ * earlier ones, zeroes the sums and synchronises the stream; they are freed
+ * by flb_destroy.  every = 0 stops sampling and keeps the sums. */
+int flb_set_correlation(flb_lattice* h, int64_t every, const int32_t* kvec, int32_t nk, int32_t nlag);
+
+/* Copy the sums to host memory: sij is nk x Q x Q complex as (re, im)
+ * doubles, index ((k Q + i) Q + j); ct is nk x nlag complex, index (k nlag + l).
+ * Either may be NULL.  *nsamples = samples taken.  Synchronises the stream.
+ * FLB_ESTATE if flb_set_correlation was never called. */
+int flb_correlation(flb_lattice* h, double* sij, double* ct, int64_t* nsamples);
+
+/* Fourier sums f_i(k) of the current state for the k-list of the last
+ * flb_set_correlation, written to host memory as nk x Q complex (re, im)
+ * doubles, index (k Q + i).  Synchronises the stream. */
+int flb_fourier_amplitudes(flb_lattice* h, double* amp);
+
 /* Block until the handle's stream has finished. */
 int flb_sync(flb_lattice* h);
 

@@ -15,6 +15,7 @@
 #include "flb_internal.hpp"
 #include "flb_kernels.hpp"
 #include "flb_stats.hpp"
+#include "flb_corr.hpp"
 
 using namespace flb;
 
@@ -280,6 +281,47 @@ void launch_moments(flb_lattice* h) {
     else if (h->d == 2) launch_moments_t<2, double>(h, (const double*)g);
     else launch_moments_t<3, double>(h, (const double*)g);
   }
+}
+
+// population correlators: Fourier sums of the current state, then one
+// accumulation step (S_ij, time correlator, ring of rho(k))
+template <int D, typename T>
+void launch_amp_t(flb_lattice* h, const T* g) {
+  const int Q = h->Q;
+  char* m = h->corr_mem;
+  const dim3 grid((unsigned)h->corr_nsb, (unsigned)((h->corr_nk + kCorrKC - 1) / kCorrKC));
+  k_amp_partial<D, T><<<grid, 256, 0, h->stream>>>(g, h->p.n[0], h->p.n[1], h->p.n[2],
+                                                    (const double*)(m + h->corr_off[1]),
+                                                    (const int32_t*)(m + h->corr_off[0]), h->corr_nk,
+                                                    h->corr_nsb, (double*)(m + h->corr_off[2]));
+  const int64_t nv = (int64_t)h->corr_nk * 2 * Q;
+  k_amp_final<<<(unsigned)((nv + 255) / 256), 256, 0, h->stream>>>((const double*)(m + h->corr_off[2]),
+                                                                   h->corr_nsb, h->corr_nk, 2 * Q,
+                                                                   (double*)(m + h->corr_off[3]));
+}
+
+void launch_amp(flb_lattice* h) {
+  const void* g = lat_buffer(h, h->cur);
+  if (h->s == 4) {
+    if (h->d == 1) launch_amp_t<1, float>(h, (const float*)g);
+    else if (h->d == 2) launch_amp_t<2, float>(h, (const float*)g);
+    else launch_amp_t<3, float>(h, (const float*)g);
+  } else {
+    if (h->d == 1) launch_amp_t<1, double>(h, (const double*)g);
+    else if (h->d == 2) launch_amp_t<2, double>(h, (const double*)g);
+    else launch_amp_t<3, double>(h, (const double*)g);
+  }
+}
+
+void corr_sample(flb_lattice* h) {
+  launch_amp(h);
+  char* m = h->corr_mem;
+  const int Q = h->Q;
+  const int64_t nt = (int64_t)h->corr_nk * Q * Q + (int64_t)h->corr_nk * h->corr_nlag;
+  k_corr_accumulate<<<(unsigned)((nt + 255) / 256), 256, 0, h->stream>>>(
+      (const double*)(m + h->corr_off[3]), h->corr_nk, Q, h->corr_nlag, h->corr_count,
+      (double*)(m + h->corr_off[4]), (double*)(m + h->corr_off[5]), (double*)(m + h->corr_off[6]));
+  h->corr_count += 1;
 }
 
 }  // namespace flb
@@ -556,6 +598,10 @@ int flb_create(const flb_params* p, void* d_pop, size_t pop_bytes, void* d_work,
   h->sample_fused = false;
   h->mom_every = 0;
   h->mom_count = 0;
+  h->corr_every = 0;
+  h->corr_nk = h->corr_nlag = h->corr_nsb = 0;
+  h->corr_count = 0;
+  h->corr_mem = nullptr;
   if (h->d >= 2) {  // twiddle tables of the axis structure factor
     double* tw = (double*)(h->work + h->wl.tw);
     const int64_t L3[3] = {p->n[0], p->n[1], p->n[2]};
@@ -581,6 +627,7 @@ int flb_destroy(flb_lattice* h) {
   DeviceGuard g(h->device);
   (void)hipStreamSynchronize(h->stream);
   if (h->own_work) (void)hipFree(h->work);
+  if (h->corr_mem) (void)hipFree(h->corr_mem);
   (void)hipHostFree(h->stage);
   delete h;
   return FLB_OK;
@@ -634,6 +681,7 @@ int flb_step(flb_lattice* h, int64_t nsteps) {
       k_add<<<1, 64, 0, h->stream>>>((const double*)(h->work + h->wl.red_out), (double*)(h->work + h->wl.momacc), kNV);
       h->mom_count += 1;
     }
+    if (h->corr_every > 0 && h->step % h->corr_every == 0) corr_sample(h);  // state before this step
     const bool sample = h->sample_every > 0 && h->step % h->sample_every == 0;
     if (sample && h->sample_fused) {
       launch_step_sampled(h, lat_buffer(h, h->cur), lat_buffer(h, nxt), t32);
@@ -779,6 +827,100 @@ int flb_sampled_moments(flb_lattice* h, flb_moments_t* sum, int64_t* nsamples) {
   sum->n_negative = (int64_t)r[38];
   sum->nonfinite = (int64_t)r[39];
   *nsamples = h->mom_count;
+  return FLB_OK;
+}
+
+int flb_set_correlation(flb_lattice* h, int64_t every, const int32_t* kvec, int32_t nk, int32_t nlag) {
+  if (!h) return fail(FLB_EINVAL, "NULL handle");
+  if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
+  if (every < 0) return fail(FLB_EINVAL, "every must be >= 0");
+  DeviceGuard g(h->device);
+  if (every == 0) {
+    h->corr_every = 0;
+    return FLB_OK;
+  }
+  if (!kvec || nk < 1 || nk > kMaxK) return fail(FLB_EINVAL, "need 1 <= nk <= %d wave vectors", kMaxK);
+  if (nlag < 1 || nlag > kMaxLag) return fail(FLB_EINVAL, "need 1 <= nlag <= %d", kMaxLag);
+  if ((int64_t)nk * nlag > kMaxKLag) return fail(FLB_EINVAL, "nk * nlag must be <= %d", kMaxKLag);
+  const int Q = h->Q;
+  const int64_t nsb = std::min<int64_t>((h->n + 255) / 256, kCorrBlocks);
+  const int64_t L = h->p.n[0] + h->p.n[1] + h->p.n[2];
+  size_t sz[7] = {sizeof(int32_t) * 3 * (size_t)nk,
+                  sizeof(double) * 2 * (size_t)L,
+                  sizeof(double) * 2 * (size_t)Q * (size_t)nk * (size_t)nsb,
+                  sizeof(double) * 2 * (size_t)Q * (size_t)nk,
+                  sizeof(double) * 2 * (size_t)Q * Q * (size_t)nk,
+                  sizeof(double) * 2 * (size_t)nk * (size_t)nlag,
+                  sizeof(double) * 2 * (size_t)nk * (size_t)nlag};
+  size_t off[7], total = 0;
+  for (int j = 0; j < 7; ++j) {
+    off[j] = total;
+    total += (sz[j] + 255) & ~(size_t)255;
+  }
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (h->corr_mem) {
+    (void)hipFree(h->corr_mem);
+    h->corr_mem = nullptr;
+  }
+  h->corr_every = 0;
+  void* mem = nullptr;
+  const hipError_t e = hipMalloc(&mem, total);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc (correlation buffers)");
+  h->corr_mem = (char*)mem;
+  std::memcpy(h->corr_off, off, sizeof off);
+  std::vector<int32_t> kin(3 * (size_t)nk);
+  for (int j = 0; j < nk; ++j)
+    for (int a = 0; a < 3; ++a) {
+      const int64_t La = h->p.n[a];
+      kin[3 * j + a] = (int32_t)(((int64_t)kvec[3 * j + a] % La + La) % La);
+    }
+  HIP_TRY(hipMemcpyAsync(h->corr_mem + off[0], kin.data(), sz[0], hipMemcpyHostToDevice, h->stream));
+  double* tw = (double*)(h->corr_mem + off[1]);
+  for (int a = 0, base = 0; a < 3; base += (int)h->p.n[a], ++a)
+    k_twiddle<<<(unsigned)((h->p.n[a] + 255) / 256), 256, 0, h->stream>>>(tw + 2 * base, h->p.n[a]);
+  for (int j = 4; j < 7; ++j) {
+    const int64_t nd = (int64_t)(sz[j] / sizeof(double));
+    k_fill_zero<<<(unsigned)((nd + 255) / 256), 256, 0, h->stream>>>((double*)(h->corr_mem + off[j]), nd);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(h->stream));  // the host k-list buffer goes out of scope
+  h->corr_nk = nk;
+  h->corr_nlag = nlag;
+  h->corr_nsb = (int)nsb;
+  h->corr_count = 0;
+  h->corr_every = every;
+  return FLB_OK;
+}
+
+int flb_correlation(flb_lattice* h, double* sij, double* ct, int64_t* nsamples) {
+  if (!h || !nsamples) return fail(FLB_EINVAL, "NULL argument");
+  if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
+  if (!h->corr_mem) return fail(FLB_ESTATE, "no correlation sampling was set up");
+  DeviceGuard g(h->device);
+  const int Q = h->Q;
+  if (sij)
+    HIP_TRY(hipMemcpyAsync(sij, h->corr_mem + h->corr_off[4], sizeof(double) * 2 * Q * Q * (size_t)h->corr_nk,
+                           hipMemcpyDeviceToHost, h->stream));
+  if (ct)
+    HIP_TRY(hipMemcpyAsync(ct, h->corr_mem + h->corr_off[6],
+                           sizeof(double) * 2 * (size_t)h->corr_nk * (size_t)h->corr_nlag,
+                           hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  *nsamples = h->corr_count;
+  return FLB_OK;
+}
+
+int flb_fourier_amplitudes(flb_lattice* h, double* amp) {
+  if (!h) return fail(FLB_EINVAL, "NULL handle");
+  if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
+  if (!h->corr_mem) return fail(FLB_ESTATE, "no correlation k-list was set up");
+  if (!amp) return fail(FLB_EINVAL, "amp is NULL");
+  DeviceGuard g(h->device);
+  launch_amp(h);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(amp, h->corr_mem + h->corr_off[3], sizeof(double) * 2 * h->Q * (size_t)h->corr_nk,
+                         hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
   return FLB_OK;
 }
 

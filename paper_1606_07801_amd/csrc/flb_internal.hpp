@@ -13,6 +13,9 @@ namespace flb {
 
 constexpr int kRedBlocks = 1024;  // blocks of the lattice-sum reduction
 constexpr int kMaxK = 1024;       // wave vectors per structure-factor list
+constexpr int kMaxLag = 65536;     // lags of the time correlator
+constexpr int kMaxKLag = 1 << 20;  // wave vectors x lags (ring and correlator: 16 B each)
+constexpr int kCorrBlocks = 256;   // site blocks of the Fourier-sum pass
 constexpr int kSkChunks = 256;    // site chunks of the direct structure factor
 constexpr int kColChunks = 64;    // row chunks of the column marginals
 constexpr int kNVals = 40;        // lattice sums (see k_moments_partial)
@@ -69,6 +72,13 @@ struct flb_lattice {
   bool sample_fused;     // the sampled step kernel produces the marginals
   int64_t mom_every;     // > 0: accumulate the lattice sums every this many steps
   int64_t mom_count;     // samples in the lattice-sum accumulator
+  // population correlators (flb_set_correlation); one library allocation
+  // holding k-list | twiddles | partials | amplitudes | S_ij | ring | C
+  int64_t corr_every;    // > 0: sample every this many steps
+  int corr_nk, corr_nlag, corr_nsb;
+  int64_t corr_count;    // samples accumulated
+  char* corr_mem;
+  size_t corr_off[7];
 };
 
 namespace flb {

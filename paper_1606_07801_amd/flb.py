@@ -26,7 +26,8 @@ EXPORTS = (
     "flb_version", "flb_last_error", "flb_lattice_constants", "flb_required_bytes",
     "flb_create", "flb_set_populations", "flb_get_populations", "flb_step",
     "flb_get_step", "flb_moments", "flb_structure_factor", "flb_set_sampling",
-    "flb_set_moment_sampling", "flb_sampled_moments", "flb_sync", "flb_destroy",
+    "flb_set_moment_sampling", "flb_sampled_moments", "flb_set_correlation",
+    "flb_correlation", "flb_fourier_amplitudes", "flb_sync", "flb_destroy",
     "flb_noise_sample", "flb_batch_create", "flb_batch_admit", "flb_batch_retire",
     "flb_batch_step", "flb_batch_size", "flb_batch_sync", "flb_batch_destroy",
 )
@@ -105,6 +106,9 @@ def load(path=LIB_PATH):
         "flb_set_sampling": ([vp, i64, vp, i32], ctypes.c_int),
         "flb_set_moment_sampling": ([vp, i64], ctypes.c_int),
         "flb_sampled_moments": ([vp, ctypes.POINTER(Moments), ctypes.POINTER(i64)], ctypes.c_int),
+        "flb_set_correlation": ([vp, i64, vp, i32, i32], ctypes.c_int),
+        "flb_correlation": ([vp, dp, dp, ctypes.POINTER(i64)], ctypes.c_int),
+        "flb_fourier_amplitudes": ([vp, dp], ctypes.c_int),
         "flb_sync": ([vp], ctypes.c_int),
         "flb_destroy": ([vp], ctypes.c_int),
         "flb_noise_sample": ([i32, i32, i32, u64, i64, i64, i64, vp, vp, vp], ctypes.c_int),
@@ -270,6 +274,36 @@ class Lattice:
         check(load().flb_sampled_moments(self.handle, ctypes.byref(m), ctypes.byref(n)))
         return self._moments_dict(m), n.value
 
+    def set_correlation(self, every, kvecs=None, nlag=1):
+        """Accumulate S_ij(k) and the density time correlator every `every`
+        steps for the wave vectors `kvecs` (nk x d integers); every = 0 stops."""
+        if every == 0:
+            check(load().flb_set_correlation(self.handle, 0, None, 0, 0))
+            return
+        kv = self._kvec(kvecs)
+        self._corr_shape = (len(kv), int(nlag))
+        check(load().flb_set_correlation(self.handle, int(every), kv.ctypes.data, len(kv), int(nlag)))
+
+    def correlation(self):
+        """(S_ij sums (nk, Q, Q) complex, C sums (nk, nlag) complex, nsamples)."""
+        n = ctypes.c_int64()
+        if getattr(self, "_corr_shape", None) is None:   # the library reports the state error
+            check(load().flb_correlation(self.handle, None, None, ctypes.byref(n)))
+        nk, nlag = self._corr_shape
+        sij = np.zeros((nk, self.Q, self.Q, 2))
+        ct = np.zeros((nk, nlag, 2))
+        check(load().flb_correlation(self.handle, sij.ctypes.data, ct.ctypes.data, ctypes.byref(n)))
+        return sij[..., 0] + 1j * sij[..., 1], ct[..., 0] + 1j * ct[..., 1], n.value
+
+    def fourier_amplitudes(self):
+        """f_i(k) of the current state for the correlation k-list: (nk, Q) complex."""
+        if getattr(self, "_corr_shape", None) is None:
+            check(load().flb_fourier_amplitudes(self.handle, None))
+        nk, _ = self._corr_shape
+        a = np.zeros((nk, self.Q, 2))
+        check(load().flb_fourier_amplitudes(self.handle, a.ctypes.data))
+        return a[..., 0] + 1j * a[..., 1]
+
     def _moments_dict(self, m):
         Q = self.Q
         ff = np.zeros((Q, Q))
@@ -287,7 +321,7 @@ class Lattice:
 
     def _kvec(self, kvecs):
         k = np.zeros((len(kvecs), 3), dtype=np.int32)
-        kk = np.asarray(kvecs, dtype=np.int64).reshape(len(kvecs), -1)
+        kk = np.asarray(kvecs, dtype=np.int64).reshape(len(kvecs), -1 if len(kvecs) else 1)
         k[:, :kk.shape[1]] = kk
         return np.ascontiguousarray(k)
 
