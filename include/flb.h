@@ -63,8 +63,14 @@ enum { FLB_NOISE_LOCAL = 0, FLB_NOISE_GLOBAL = 1, FLB_NOISE_OFF = 2 };
 enum { FLB_LAW_GAUSS = 0, FLB_LAW_UNIFORM = 1 };
 /* storage scheme: two buffers with pull streaming (the only one so far) */
 enum { FLB_LAYOUT_TWO_BUFFER = 0 };
-/* kernel variants of the step (all give bit-identical results) */
-enum { FLB_KERNEL_AUTO = 0, FLB_KERNEL_PLAIN = 1, FLB_KERNEL_ROWS = 2, FLB_KERNEL_FLAT = 3 };
+/* kernel variants of the step (all give bit-identical results).  RESIDENT:
+ * one workgroup keeps the whole lattice in LDS and runs up to 65536 steps per
+ * launch, with the sampled statistics taken inside; for lattices of at most
+ * 4096 sites whose state, densities and twiddles fit the device's LDS per
+ * workgroup (EINVAL at flb_create otherwise).  AUTO picks RESIDENT when it
+ * fits, else ROWS. */
+enum { FLB_KERNEL_AUTO = 0, FLB_KERNEL_PLAIN = 1, FLB_KERNEL_ROWS = 2, FLB_KERNEL_FLAT = 3,
+       FLB_KERNEL_RESIDENT = 4 };
 
 typedef struct flb_lattice flb_lattice; /* opaque */
 typedef struct flb_batch flb_batch;     /* opaque */

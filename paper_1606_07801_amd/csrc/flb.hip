@@ -16,6 +16,7 @@
 #include "flb_kernels.hpp"
 #include "flb_stats.hpp"
 #include "flb_corr.hpp"
+#include "flb_resident.hpp"
 
 using namespace flb;
 
@@ -76,7 +77,8 @@ int check_params(const flb_params* p) {
   if (p->noise < 0 || p->noise > 2) return fail(FLB_EINVAL, "noise must be 0 (local), 1 (global) or 2 (off)");
   if (p->noise_law < 0 || p->noise_law > 1) return fail(FLB_EINVAL, "noise_law must be 0 (Gauss) or 1 (uniform)");
   if (p->layout != FLB_LAYOUT_TWO_BUFFER) return fail(FLB_EINVAL, "layout must be FLB_LAYOUT_TWO_BUFFER");
-  if (p->kernel < 0 || p->kernel > 3) return fail(FLB_EINVAL, "kernel must be 0 (auto), 1 (plain), 2 (rows) or 3 (flat)");
+  if (p->kernel < 0 || p->kernel > 4)
+    return fail(FLB_EINVAL, "kernel must be 0 (auto), 1 (plain), 2 (rows), 3 (flat) or 4 (resident)");
   if (p->kernel == FLB_KERNEL_FLAT && (p->tile_rows > 8 || n * (2 * d + 1) * p->precision >= 4294967296.0))
     return fail(FLB_EINVAL, "flat kernel: tile_rows <= 8 and Q * N * precision < 2^32");
   if (p->tile_x != 0 && (p->tile_x < 64 || p->tile_x > 1024 || p->tile_x % 64 != 0))
@@ -146,10 +148,10 @@ WorkLayout work_layout(const flb_params& p) {
     L.rowsum = take(sizeof(double) * nrows);
     L.colpart = take(sizeof(double) * std::min<int64_t>(kColChunks, nrows) * nx);
     L.marg = take(sizeof(double) * (nx + ny + nz));
-    L.tw = take(sizeof(double) * 2 * (nx + ny + nz));
     L.rowpart = take(sizeof(double) * ((nx + 255) / 256) * nrows);
     L.colbig = take(sizeof(double) * ((nrows + kSampleRows - 1) / kSampleRows) * nx);
   }
+  L.tw = take(sizeof(double) * 2 * (nx + ny + nz));
   L.skpart = take(sizeof(double) * 2 * (size_t)kMaxK * kSkChunks);
   for (int s = 0; s < 2; ++s) {
     L.kinfo[s] = take(sizeof(int64_t) * 2 * kMaxK);
@@ -281,6 +283,81 @@ void launch_moments(flb_lattice* h) {
     else if (h->d == 2) launch_moments_t<2, double>(h, (const double*)g);
     else launch_moments_t<3, double>(h, (const double*)g);
   }
+}
+
+// resident small lattice: `c` steps in one launch, sampling inside
+int64_t multiples_in(int64_t t0, int64_t c, int64_t every) {
+  if (every <= 0 || c <= 0) return 0;
+  const int64_t first = (t0 + every - 1) / every * every, last = t0 + c - 1;
+  return first > last ? 0 : (last - first) / every + 1;
+}
+
+template <int D, typename T, int SPT>
+void launch_resident_spt(flb_lattice* h, const ResArgs& A) {
+  static bool attr = false;  // raise the dynamic LDS limit once per instantiation
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_resident<D, T, SPT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              h->res_lds_max);
+    (void)hipGetLastError();
+    attr = true;
+  }
+  k_resident<D, T, SPT><<<1, kResThreads, h->res_lds, h->stream>>>(make_kparams<T>(h->p, h->rho_eq), A);
+}
+
+template <int D, typename T>
+void launch_resident_t(flb_lattice* h, const ResArgs& A) {
+  if (h->n <= kResThreads) launch_resident_spt<D, T, 1>(h, A);
+  else if (h->n <= 2 * kResThreads) launch_resident_spt<D, T, 2>(h, A);
+  else launch_resident_spt<D, T, 4>(h, A);
+}
+
+void launch_resident(flb_lattice* h, int c) {
+  char* w = h->work;
+  ResArgs A{};
+  A.gin = lat_buffer(h, h->cur);
+  A.gout = lat_buffer(h, (h->cur + c) & 1);
+  A.nx = (int32_t)h->p.n[0];
+  A.ny = (int32_t)h->p.n[1];
+  A.nz = (int32_t)h->p.n[2];
+  A.nsteps = c;
+  A.step0 = h->step;
+  A.mom_every = h->mom_every;
+  A.momacc = (double*)(w + h->wl.momacc);
+  A.sk_every = h->sample_every;
+  A.nax = h->nax[1];
+  A.ngen = h->ngen[1];
+  A.kinfo = (const int64_t*)(w + h->wl.kinfo[1]);
+  A.slot_ax = (const int32_t*)(w + h->wl.slot_ax[1]);
+  A.kv = (const int64_t*)(w + h->wl.kv[1]);
+  A.slot_gen = (const int32_t*)(w + h->wl.slot_gen[1]);
+  A.skacc = (double*)(w + h->wl.skacc);
+  A.corr_every = h->corr_mem ? h->corr_every : 0;
+  if (h->corr_mem) {
+    char* m = h->corr_mem;
+    A.cnk = h->corr_nk;
+    A.nlag = h->corr_nlag;
+    A.corr_s0 = h->corr_count;
+    A.ckinfo = (const int32_t*)(m + h->corr_off[0]);
+    A.amp = (double*)(m + h->corr_off[3]);
+    A.sij = (double*)(m + h->corr_off[4]);
+    A.ring = (double*)(m + h->corr_off[5]);
+    A.ct = (double*)(m + h->corr_off[6]);
+  }
+  A.tw = (const double*)(w + h->wl.tw);
+  if (h->s == 4) {
+    if (h->d == 1) launch_resident_t<1, float>(h, A);
+    else if (h->d == 2) launch_resident_t<2, float>(h, A);
+    else launch_resident_t<3, float>(h, A);
+  } else {
+    if (h->d == 1) launch_resident_t<1, double>(h, A);
+    else if (h->d == 2) launch_resident_t<2, double>(h, A);
+    else launch_resident_t<3, double>(h, A);
+  }
+  h->mom_count += multiples_in(h->step, c, h->mom_every);
+  h->sk_count += multiples_in(h->step, c, h->sample_every);
+  h->corr_count += multiples_in(h->step, c, A.corr_every);
+  h->cur = (h->cur + c) & 1;
+  h->step += c;
 }
 
 // population correlators: Fourier sums of the current state, then one
@@ -583,6 +660,22 @@ int flb_create(const flb_params* p, void* d_pop, size_t pop_bytes, void* d_work,
     delete h;
     return hip_fail(e, "hipGetDevice");
   }
+  {  // one workgroup keeps the whole lattice in LDS when it fits
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) != hipSuccess)
+      lds_max = 0;
+    (void)hipGetLastError();
+    const size_t need = res_lds_bytes(h->n, h->Q, (int)h->s, p->n[0] + p->n[1] + p->n[2]);
+    const bool fits = h->n <= kResMaxSites && need <= (size_t)lds_max;
+    if (p->kernel == FLB_KERNEL_RESIDENT && !fits) {
+      delete h;
+      return fail(FLB_EINVAL, "resident kernel: the lattice needs %zu bytes of LDS (limit %d) or has more than %d sites",
+                  need, lds_max, kResMaxSites);
+    }
+    h->resident = fits && (p->kernel == FLB_KERNEL_AUTO || p->kernel == FLB_KERNEL_RESIDENT);
+    h->res_lds = need;
+    h->res_lds_max = lds_max;
+  }
   if (d_work) {
     h->work = (char*)d_work;
     h->own_work = false;
@@ -602,7 +695,7 @@ int flb_create(const flb_params* p, void* d_pop, size_t pop_bytes, void* d_work,
   h->corr_nk = h->corr_nlag = h->corr_nsb = 0;
   h->corr_count = 0;
   h->corr_mem = nullptr;
-  if (h->d >= 2) {  // twiddle tables of the axis structure factor
+  {  // twiddle tables of the structure factor and of the resident kernel
     double* tw = (double*)(h->work + h->wl.tw);
     const int64_t L3[3] = {p->n[0], p->n[1], p->n[2]};
     int64_t off = 0;
@@ -673,6 +766,15 @@ int flb_step(flb_lattice* h, int64_t nsteps) {
   if (nsteps < 0) return fail(FLB_EINVAL, "nsteps must be >= 0");
   if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
   DeviceGuard g(h->device);
+  if (h->resident) {
+    for (int64_t k = 0; k < nsteps;) {
+      const int c = (int)std::min<int64_t>(nsteps - k, kResMaxChunk);
+      launch_resident(h, c);
+      k += c;
+    }
+    HIP_TRY(hipGetLastError());
+    return FLB_OK;
+  }
   for (int64_t k = 0; k < nsteps; ++k) {
     const int nxt = 1 - h->cur;
     const uint32_t t32 = (uint32_t)(h->step & 0xFFFFFFFF);

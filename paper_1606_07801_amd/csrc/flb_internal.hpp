@@ -79,6 +79,10 @@ struct flb_lattice {
   int64_t corr_count;    // samples accumulated
   char* corr_mem;
   size_t corr_off[7];
+  // small lattices: one workgroup steps the whole lattice in LDS
+  bool resident;
+  size_t res_lds;        // its LDS bytes
+  int res_lds_max;       // the device's LDS bytes per workgroup
 };
 
 namespace flb {
