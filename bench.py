@@ -250,18 +250,48 @@ def _timed(torch, fn, steps):
 
 
 def bench_d1q3(torch, flb, inputs, tune, args):
-    """D1Q3, FP64, L = 256, 10^4 steps, Poisson counts at rho = 10."""
+    """D1Q3, FP64, L = 256, 10^4 steps, Poisson counts at rho = 10, with the
+    lattice sums and S(k) of all 255 nonzero modes taken every step; also
+    timed without sampling."""
     dims = (256,)
     w, _ = flb.constants(1)
-    L = flb.Lattice(1, dims, precision=8, omega=1.0, seed=0, **tune.best_config(1, 8, dims))
-    L.set_populations(inputs.poisson_counts(dims, 10.0 * w, seed=0))
-    L.step(args.warmup)
+    cfg = tune.best_config(1, 8, dims)
+    f0 = inputs.poisson_counts(dims, 10.0 * w, seed=0)
     steps = 10_000
+    L = flb.Lattice(1, dims, precision=8, omega=1.0, seed=0, **cfg)
+    L.set_populations(f0)
+    L.step(args.warmup)
+    ms_plain = _timed(torch, L.step, steps)
+    L.close()
+    L = flb.Lattice(1, dims, precision=8, omega=1.0, seed=0, **cfg)
+    L.set_populations(f0)
+    ks = [[k] for k in range(1, 256)]
+    L.set_moment_sampling(1)
+    L.set_sampling(1, ks)
     ms = _timed(torch, L.step, steps)
+    sums, n = L.sampled_moments()
+    S = L.structure_factor(mode="read")[:255]
     m = L.moments()
     L.close()
-    return {"workload": "D1Q3 256 fp64 rho=10 Poisson, omega=1, 10^4 steps", "ms_per_step": round(ms, 5),
-            "mlups": round(256 / (ms * 1e-3) / 1e6, 2), "mass_drift": m["mass"] - m["mass0"]}
+    return {"workload": "D1Q3 256 fp64 rho=10 Poisson, omega=1, 10^4 steps, lattice sums and S(k) of all 255 "
+                        "k != 0 every step", "kernel": cfg, "ms_per_step": round(ms, 6),
+            "mlups": round(256 / ms / 1e3, 2), "ms_per_step_unsampled": round(ms_plain, 6),
+            "mlups_unsampled": round(256 / ms_plain / 1e3, 2), "samples": n,
+            "mass_drift": m["mass"] - m["mass0"], "mean_mass": sums["mass"] / n,
+            "sk_mean_over_rho": round(float(S.mean() / (m["mass"] / 256)), 4),
+            "ms_per_step_one_launch_per_step": round(_d1q3_launch_per_step(torch, flb, f0, ks), 6)}
+
+
+def _d1q3_launch_per_step(torch, flb, f0, ks):
+    """The same sampled run on the HBM kernels (one launch per step and per
+    statistic), for comparison."""
+    L = flb.Lattice(1, (256,), precision=8, omega=1.0, seed=0, kernel="flat", tile_rows=1)
+    L.set_populations(f0)
+    L.set_moment_sampling(1)
+    L.set_sampling(1, ks)
+    ms = _timed(torch, L.step, 2000)
+    L.close()
+    return ms
 
 
 def bench_d3q7(torch, flb, inputs, tune, args):

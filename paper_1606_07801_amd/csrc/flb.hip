@@ -292,8 +292,29 @@ int64_t multiples_in(int64_t t0, int64_t c, int64_t every) {
   return first > last ? 0 : (last - first) / every + 1;
 }
 
+// LDS bytes of a resident launch with the current sampling set-up, and
+// whether the correlator arrays go to LDS; false when even the tables do not
+// fit (flb_step then uses the HBM kernels).
+bool resident_lds(const flb_lattice* h, size_t* lds, int* corr_lds) {
+  const int ne = h->sample_every > 0 ? h->nk[1] : 0;
+  const int cnk = h->corr_mem && h->corr_every > 0 ? h->corr_nk : 0;
+  const size_t with = h->res_lds + res_extra_bytes(ne, cnk, h->Q, h->corr_nlag, cnk > 0);
+  const size_t without = h->res_lds + res_extra_bytes(ne, cnk, h->Q, h->corr_nlag, false);
+  if (with <= (size_t)h->res_lds_max) {
+    *lds = with;
+    *corr_lds = cnk > 0;
+    return true;
+  }
+  if (without <= (size_t)h->res_lds_max) {
+    *lds = without;
+    *corr_lds = 0;
+    return true;
+  }
+  return false;
+}
+
 template <int D, typename T, int SPT>
-void launch_resident_spt(flb_lattice* h, const ResArgs& A) {
+void launch_resident_spt(flb_lattice* h, const ResArgs& A, size_t lds) {
   static bool attr = false;  // raise the dynamic LDS limit once per instantiation
   if (!attr) {
     (void)hipFuncSetAttribute((const void*)k_resident<D, T, SPT>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -301,17 +322,17 @@ void launch_resident_spt(flb_lattice* h, const ResArgs& A) {
     (void)hipGetLastError();
     attr = true;
   }
-  k_resident<D, T, SPT><<<1, kResThreads, h->res_lds, h->stream>>>(make_kparams<T>(h->p, h->rho_eq), A);
+  k_resident<D, T, SPT><<<1, kResThreads, lds, h->stream>>>(make_kparams<T>(h->p, h->rho_eq), A);
 }
 
 template <int D, typename T>
-void launch_resident_t(flb_lattice* h, const ResArgs& A) {
-  if (h->n <= kResThreads) launch_resident_spt<D, T, 1>(h, A);
-  else if (h->n <= 2 * kResThreads) launch_resident_spt<D, T, 2>(h, A);
-  else launch_resident_spt<D, T, 4>(h, A);
+void launch_resident_t(flb_lattice* h, const ResArgs& A, size_t lds) {
+  if (h->n <= kResThreads) launch_resident_spt<D, T, 1>(h, A, lds);
+  else if (h->n <= 2 * kResThreads) launch_resident_spt<D, T, 2>(h, A, lds);
+  else launch_resident_spt<D, T, 4>(h, A, lds);
 }
 
-void launch_resident(flb_lattice* h, int c) {
+void launch_resident(flb_lattice* h, int c, size_t lds, int corr_lds) {
   char* w = h->work;
   ResArgs A{};
   A.gin = lat_buffer(h, h->cur);
@@ -331,6 +352,26 @@ void launch_resident(flb_lattice* h, int c) {
   A.kv = (const int64_t*)(w + h->wl.kv[1]);
   A.slot_gen = (const int32_t*)(w + h->wl.slot_gen[1]);
   A.skacc = (double*)(w + h->wl.skacc);
+  A.sk_fft = 0;
+  A.sk_dft = 0;
+  if (h->sample_every > 0) {  // axes with entries, power-of-two extent that fits the FFT scratch
+    for (int pass = 0; pass < 2; ++pass)
+      for (int j = 0; j < h->nk[1]; ++j) {
+        int nnz = 0, ax = -1;
+        for (int a = 0; a < 3; ++a) {
+          const int64_t La = h->p.n[a];
+          if ((((int64_t)h->klist[1][3 * j + a] % La) + La) % La != 0) {
+            ++nnz;
+            ax = a;
+          }
+        }
+        const int64_t L = nnz == 1 ? h->p.n[ax] : 0;
+        const bool fft = nnz == 1 && L >= 2 && (L & (L - 1)) == 0 && 2 * L <= kResScratch;
+        if (pass == 0 && fft) A.sk_fft |= 1 << ax;
+        if (pass == 1 && nnz > 0 && !(nnz == 1 && (A.sk_fft & (1 << ax)))) A.sk_dft = 1;
+      }
+  }
+  A.corr_lds = corr_lds;
   A.corr_every = h->corr_mem ? h->corr_every : 0;
   if (h->corr_mem) {
     char* m = h->corr_mem;
@@ -345,13 +386,13 @@ void launch_resident(flb_lattice* h, int c) {
   }
   A.tw = (const double*)(w + h->wl.tw);
   if (h->s == 4) {
-    if (h->d == 1) launch_resident_t<1, float>(h, A);
-    else if (h->d == 2) launch_resident_t<2, float>(h, A);
-    else launch_resident_t<3, float>(h, A);
+    if (h->d == 1) launch_resident_t<1, float>(h, A, lds);
+    else if (h->d == 2) launch_resident_t<2, float>(h, A, lds);
+    else launch_resident_t<3, float>(h, A, lds);
   } else {
-    if (h->d == 1) launch_resident_t<1, double>(h, A);
-    else if (h->d == 2) launch_resident_t<2, double>(h, A);
-    else launch_resident_t<3, double>(h, A);
+    if (h->d == 1) launch_resident_t<1, double>(h, A, lds);
+    else if (h->d == 2) launch_resident_t<2, double>(h, A, lds);
+    else launch_resident_t<3, double>(h, A, lds);
   }
   h->mom_count += multiples_in(h->step, c, h->mom_every);
   h->sk_count += multiples_in(h->step, c, h->sample_every);
@@ -766,10 +807,12 @@ int flb_step(flb_lattice* h, int64_t nsteps) {
   if (nsteps < 0) return fail(FLB_EINVAL, "nsteps must be >= 0");
   if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
   DeviceGuard g(h->device);
-  if (h->resident) {
+  size_t lds = 0;
+  int corr_lds = 0;
+  if (h->resident && resident_lds(h, &lds, &corr_lds)) {
     for (int64_t k = 0; k < nsteps;) {
       const int c = (int)std::min<int64_t>(nsteps - k, kResMaxChunk);
-      launch_resident(h, c);
+      launch_resident(h, c, lds, corr_lds);
       k += c;
     }
     HIP_TRY(hipGetLastError());

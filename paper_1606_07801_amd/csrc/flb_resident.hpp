@@ -49,6 +49,9 @@ struct ResArgs {
   const int64_t* kv;
   const int32_t* slot_gen;
   double* skacc;
+  int32_t sk_fft;  // bit a: axis-a entries by FFT of the marginal
+  int32_t sk_dft;  // some entries need the DFT / direct-sum pass
+  int32_t corr_lds;  // correlator arrays held in LDS for the launch
   // population correlators
   int64_t corr_every;
   int32_t cnk, nlag;
@@ -65,9 +68,38 @@ struct ResArgs {
 // LDS bytes of a resident lattice: state, densities, marginals, twiddles,
 // scratch (the host checks this against the device limit).
 __host__ __device__ constexpr size_t res_state_bytes(size_t q_n_s) { return (q_n_s + 15) & ~(size_t)15; }
+// (densities and marginals padded to even lengths: every region after the
+// state starts 16-byte aligned)
 __host__ __device__ constexpr size_t res_lds_bytes(int64_t n, int q, int s, int64_t lsum) {
-  return res_state_bytes((size_t)q * (size_t)n * (size_t)s) + 8 * (size_t)n + 8 * (size_t)lsum +
-         16 * (size_t)lsum + 8 * (size_t)kResScratch;
+  return res_state_bytes((size_t)q * (size_t)n * (size_t)s) + 8 * (size_t)((n + 1) & ~1ll) +
+         8 * (size_t)((lsum + 1) & ~1ll) + 16 * (size_t)lsum + 8 * (size_t)kResScratch;
+}
+
+// Sum over the 64 lanes of a wave with DPP lane moves (no LDS traffic):
+// quad swaps, half-row and row mirrors leave every lane with its 16-lane row
+// sum; the four row sums are read from lanes 0, 16, 32, 48 and added in that
+// order.  The result is uniform across the wave.
+template <int CTRL>
+__device__ __forceinline__ double res_dpp(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double res_lane(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double res_wave_sum(double v) {
+  v += res_dpp<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += res_dpp<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += res_dpp<0x141>(v);  // row_half_mirror
+  v += res_dpp<0x140>(v);  // row_mirror
+  return ((res_lane(v, 0) + res_lane(v, 16)) + res_lane(v, 32)) + res_lane(v, 48);
 }
 
 // Largest power of two p <= cap with items * p <= kResThreads (at least 1).
@@ -81,7 +113,7 @@ __device__ __forceinline__ int res_parts(int items, int cap) {
 //   sum_{x in [x0, x1)} (m[x] - mean) (cos, sgn sin)(2 pi k x / L)
 __device__ __forceinline__ void res_line_dft(const double* m, int x0, int x1, int L, int k, double mean,
                                              const double* tw, double sgn, double& re, double& im) {
-  int p = (int)(((int64_t)k * x0) % L);
+  int p = (int)(((unsigned)k * (unsigned)x0) % (unsigned)L);  // k, x0 < L <= 4096
   for (int x = x0; x < x1; ++x) {
     const double v = m[x] - mean;
     re += v * tw[2 * p];
@@ -91,13 +123,28 @@ __device__ __forceinline__ void res_line_dft(const double* m, int x0, int x1, in
   }
 }
 
+// Lattice-sum slots a model uses: mass, sum f_i (Q), sum f_i f_j (i <= j),
+// sum rho^2, sum rho^+, #rho < 0, #non-finite; the other of the 40 stay zero.
+template <int D>
+struct ResMom {
+  static constexpr int Q = 2 * D + 1;
+  static constexpr int NFF = Q * (Q + 1) / 2;
+  static constexpr int NV = 1 + Q + NFF + 4;
+  __device__ static constexpr int slot(int v) {
+    return v == 0 ? 0 : (v <= Q ? v : (v <= Q + NFF ? 8 + (v - Q - 1) : 36 + (v - Q - NFF - 1)));
+  }
+};
+
+// Adds this sample's lattice sums to mom (LDS, 40 slots).  Only waves that
+// hold sites reduce (site = tid + 1024 j, so wave w holds sites iff 64 w < N).
 template <int D, typename T, int SPT>
-__device__ __forceinline__ void res_sample_moments(const T* st, int N, double* scr, double* momacc,
+__device__ __forceinline__ void res_sample_moments(const T* st, int N, double* scr, double* mom,
                                                    const int (&sites)[SPT]) {
-  constexpr int Q = 2 * D + 1;
-  double acc[kNV];
+  using M = ResMom<D>;
+  constexpr int Q = M::Q;
+  double acc[M::NV];
 #pragma unroll
-  for (int v = 0; v < kNV; ++v) acc[v] = 0.0;
+  for (int v = 0; v < M::NV; ++v) acc[v] = 0.0;
 #pragma unroll
   for (int j = 0; j < SPT; ++j) {
     const int s = sites[j];
@@ -109,31 +156,64 @@ __device__ __forceinline__ void res_sample_moments(const T* st, int N, double* s
       f[i] = (double)st[i * N + s];
       rho += f[i];
       acc[1 + i] += f[i];
-      acc[39] += isfinite(f[i]) ? 0.0 : 1.0;
+      acc[M::NV - 1] += isfinite(f[i]) ? 0.0 : 1.0;
     }
     int k = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i)
 #pragma unroll
-      for (int l = i; l < Q; ++l) acc[8 + k++] += f[i] * f[l];
+      for (int l = i; l < Q; ++l) acc[1 + Q + k++] += f[i] * f[l];
     acc[0] += rho;
-    acc[36] += rho * rho;
-    acc[37] += rho > 0 ? rho : 0.0;
-    acc[38] += rho < 0 ? 1.0 : 0.0;
+    acc[1 + Q + M::NFF] += rho * rho;
+    acc[2 + Q + M::NFF] += rho > 0 ? rho : 0.0;
+    acc[3 + Q + M::NFF] += rho < 0 ? 1.0 : 0.0;
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nwa = (N + 63) / 64 < kResWaves ? (N + 63) / 64 : kResWaves;
+  if (wave < nwa) {
 #pragma unroll
-  for (int v = 0; v < kNV; ++v) {
-    const double r = wave_sum(acc[v]);
-    if (lane == 0) scr[wave * kNV + v] = r;
+    for (int v = 0; v < M::NV; ++v) {
+      const double r = res_wave_sum(acc[v]);
+      if (lane == 0) scr[wave * M::NV + v] = r;
+    }
   }
   __syncthreads();
-  if (threadIdx.x < kNV) {
+  if (threadIdx.x < M::NV) {
     double r = 0;
-    for (int w = 0; w < kResWaves; ++w) r += scr[w * kNV + threadIdx.x];
-    momacc[threadIdx.x] += r;
+    for (int w = 0; w < nwa; ++w) r += scr[w * M::NV + threadIdx.x];
+    mom[M::slot(threadIdx.x)] += r;
   }
   __syncthreads();
+}
+
+// In-place radix-2 FFT of a line: X (2 L doubles, complex) receives
+// sum_x (m[x] - mean) e^{-2 pi i k x / L} at index k.  L a power of two;
+// tw holds (cos, sin)(2 pi j / L).  Whole-workgroup barriers between stages.
+__device__ __forceinline__ void res_fft_line(double* X, const double* m, int L, double mean, const double* tw) {
+  int lg = 0;
+  while ((1 << lg) < L) ++lg;
+  for (int x = threadIdx.x; x < L; x += kResThreads) {
+    const int r = (int)(__brev((unsigned)x) >> (32 - lg));
+    X[2 * r] = m[x] - mean;
+    X[2 * r + 1] = 0.0;
+  }
+  __syncthreads();
+  for (int half = 1; half < L; half *= 2) {
+    const int stride = L / (2 * half);
+    for (int b = threadIdx.x; b < L / 2; b += kResThreads) {
+      const int j = b & (half - 1);
+      const int i0 = (b - j) * 2 + j, i1 = i0 + half;
+      const double c = tw[2 * j * stride], sn = -tw[2 * j * stride + 1];
+      const double xr = X[2 * i1], xi = X[2 * i1 + 1];
+      const double tr = c * xr - sn * xi, ti = c * xi + sn * xr;
+      const double ur = X[2 * i0], ui = X[2 * i0 + 1];
+      X[2 * i0] = ur + tr;
+      X[2 * i0 + 1] = ui + ti;
+      X[2 * i1] = ur - tr;
+      X[2 * i1 + 1] = ui - ti;
+    }
+    __syncthreads();
+  }
 }
 
 // Twiddle of k.x for a general wave vector (components reduced modulo L_a),
@@ -141,18 +221,18 @@ __device__ __forceinline__ void res_sample_moments(const T* st, int N, double* s
 template <int D>
 __device__ __forceinline__ void res_twiddle(const double* tw, int nx, int ny, int nz, int kx, int ky, int kz,
                                             int x, int y, int z, double sgn, double& c, double& s) {
-  int m = (int)(((int64_t)kx * x) % nx);
+  int m = (int)(((unsigned)kx * (unsigned)x) % (unsigned)nx);  // all below 4096
   c = tw[2 * m];
   s = tw[2 * m + 1];
   if constexpr (D >= 2) {
-    m = (int)(((int64_t)ky * y) % ny);
+    m = (int)(((unsigned)ky * (unsigned)y) % (unsigned)ny);
     const double ar = tw[2 * (nx + m)], ai = tw[2 * (nx + m) + 1];
     const double t = c * ar - s * ai;
     s = c * ai + s * ar;
     c = t;
   }
   if constexpr (D >= 3) {
-    m = (int)(((int64_t)kz * z) % nz);
+    m = (int)(((unsigned)kz * (unsigned)z) % (unsigned)nz);
     const double ar = tw[2 * (nx + ny + m)], ai = tw[2 * (nx + ny + m) + 1];
     const double t = c * ar - s * ai;
     s = c * ai + s * ar;
@@ -161,11 +241,36 @@ __device__ __forceinline__ void res_twiddle(const double* tw, int nx, int ny, in
   s *= sgn;
 }
 
+// LDS tables and accumulators that live for one launch (after the scratch):
+//   mom[40]      lattice sums of this launch's samples
+//   skl[ne]      S(k) sums of this launch's samples (ne padded to even)
+//   ent[ne]      k-list entries: (code, kx, ky, kz); code -1: k = 0, a >= 0:
+//                along axis a, -2: general
+//   eslot[ne]    output slot of each entry (ne padded to a multiple of 4)
+//   cki[cnk]     correlator wave vectors (kx, ky, kz, 0)
+//   corr         if corr_lds: amp (2 Q cnk) | sij (2 Q Q cnk) | ct, ring (2 cnk nlag each)
+__host__ __device__ constexpr size_t res_extra_bytes(int ne, int cnk, int q, int nlag, bool corr_lds) {
+  return 8 * (size_t)kNV + 8 * (size_t)((ne + 1) & ~1) + 16 * (size_t)ne + 4 * (size_t)((ne + 3) & ~3) +
+         16 * (size_t)cnk +
+         (corr_lds ? 16 * ((size_t)q * cnk + (size_t)q * q * cnk + 2 * (size_t)cnk * nlag) : 0);
+}
+
+struct ResLocal {
+  double* mom;
+  double* skl;
+  int4* ent;
+  int* eslot;
+  int4* cki;
+  double *amp, *sij, *ct, *ring;  // LDS or HBM
+};
+
 template <int D, typename T, int SPT>
-__device__ __forceinline__ void res_sample_sk(const ResArgs& A, const T* st, double* rho, double* marg,
-                                              const double* tw, double* scr, const int (&sites)[SPT]) {
+__device__ __forceinline__ void res_sample_sk(const ResArgs& A, const ResLocal& R, const T* st, double* rho,
+                                              double* marg, const double* tw, double* scr,
+                                              const int (&sites)[SPT]) {
   constexpr int Q = 2 * D + 1;
   const int nx = A.nx, ny = A.ny, nz = A.nz, N = nx * ny * nz;
+  const int ne = A.nax + A.ngen;
   double part = 0;
 #pragma unroll
   for (int j = 0; j < SPT; ++j) {
@@ -178,16 +283,18 @@ __device__ __forceinline__ void res_sample_sk(const ResArgs& A, const T* st, dou
     part += r;
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  part = wave_sum(part);
+  part = res_wave_sum(part);
   if (lane == 0) scr[wave] = part;
   __syncthreads();
   double M = 0;
   for (int w = 0; w < kResWaves; ++w) M += scr[w];
   const double mean = M / (double)N;
+  for (int e = threadIdx.x; e < ne; e += kResThreads)  // k = 0: the squared mass
+    if (R.ent[e].x == -1) R.skl[e] += M * M / (double)N;
   double* mx = marg;
   double* my = marg + nx;
   double* mz = my + ny;
-  __syncthreads();  // rho complete
+  __syncthreads();  // every thread has read the mass partials
   if constexpr (D >= 2) {  // axis marginals from rho, each a fixed-order sum
     for (int x = threadIdx.x; x < nx; x += kResThreads) {
       double a = 0;
@@ -208,30 +315,44 @@ __device__ __forceinline__ void res_sample_sk(const ResArgs& A, const T* st, dou
         mz[z] = a;
       }
     }
+    __syncthreads();
   }
-  __syncthreads();
-  const int ne = A.nax + A.ngen;
+  // axes whose entries come from an FFT of the marginal (bit a of sk_fft:
+  // power-of-two extent that fits the scratch)
+  for (int a = 0; a < D; ++a) {
+    if (!(A.sk_fft & (1 << a))) continue;
+    const int L = a == 0 ? nx : (a == 1 ? ny : nz);
+    const double* m = D == 1 ? rho : (a == 0 ? mx : (a == 1 ? my : mz));
+    res_fft_line(scr, m, L, M / (double)L, tw + 2 * (a == 0 ? 0 : (a == 1 ? nx : nx + ny)));
+    for (int e = threadIdx.x; e < ne; e += kResThreads) {
+      const int4 en = R.ent[e];
+      if (en.x != a) continue;
+      const int k = a == 0 ? en.y : (a == 1 ? en.z : en.w);
+      R.skl[e] += (scr[2 * k] * scr[2 * k] + scr[2 * k + 1] * scr[2 * k + 1]) / (double)N;
+    }
+    __syncthreads();
+  }
+  if (!A.sk_dft) return;
+  // the remaining entries: DFT of the marginal along one axis, or the direct
+  // sum over the sites for a general wave vector
   const int parts = res_parts(ne, 64);
   for (int t = threadIdx.x; t < ne * parts; t += kResThreads) {
     const int e = t / parts, p = t % parts;
+    const int4 en = R.ent[e];
     double re = 0, im = 0;
-    if (e < A.nax) {
-      const int axis = (int)A.kinfo[2 * e];
-      if (axis >= 0) {
-        const int k = (int)A.kinfo[2 * e + 1];
-        const int L = axis == 0 ? nx : (axis == 1 ? ny : nz);
-        const double* m = D == 1 ? rho : (axis == 0 ? mx : (axis == 1 ? my : mz));
-        const double* twa = tw + 2 * (axis == 0 ? 0 : (axis == 1 ? nx : nx + ny));
-        const int x0 = (int)((int64_t)L * p / parts), x1 = (int)((int64_t)L * (p + 1) / parts);
-        res_line_dft(m, x0, x1, L, k, M / (double)L, twa, -1.0, re, im);
-      }
-    } else {
-      const int64_t* kk = A.kv + 3 * (e - A.nax);
-      const int kx = (int)kk[0], ky = (int)kk[1], kz = (int)kk[2];
+    if (en.x >= 0 && !(A.sk_fft & (1 << en.x))) {
+      const int a = en.x;
+      const int L = a == 0 ? nx : (a == 1 ? ny : nz);
+      const int k = a == 0 ? en.y : (a == 1 ? en.z : en.w);
+      const double* m = D == 1 ? rho : (a == 0 ? mx : (a == 1 ? my : mz));
+      const double* twa = tw + 2 * (a == 0 ? 0 : (a == 1 ? nx : nx + ny));
+      const int x0 = L * p / parts, x1 = L * (p + 1) / parts;
+      res_line_dft(m, x0, x1, L, k, M / (double)L, twa, -1.0, re, im);
+    } else if (en.x == -2) {
       for (int s = p; s < N; s += parts) {
         const int x = s % nx, yz = s / nx, y = yz % ny, z = yz / ny;
         double c, sn;
-        res_twiddle<D>(tw, nx, ny, nz, kx, ky, kz, x, y, z, -1.0, c, sn);
+        res_twiddle<D>(tw, nx, ny, nz, en.y, en.z, en.w, x, y, z, -1.0, c, sn);
         const double v = rho[s] - mean;
         re += v * c;
         im += v * sn;
@@ -242,28 +363,21 @@ __device__ __forceinline__ void res_sample_sk(const ResArgs& A, const T* st, dou
   }
   __syncthreads();
   for (int e = threadIdx.x; e < ne; e += kResThreads) {
+    const int4 en = R.ent[e];
+    if (en.x == -1 || (en.x >= 0 && (A.sk_fft & (1 << en.x)))) continue;
     double re = 0, im = 0;
     for (int p = 0; p < parts; ++p) {
       re += scr[2 * (e * parts + p)];
       im += scr[2 * (e * parts + p) + 1];
     }
-    bool k0;
-    int slot;
-    if (e < A.nax) {
-      k0 = A.kinfo[2 * e] < 0;
-      slot = A.slot_ax[e];
-    } else {
-      const int64_t* kk = A.kv + 3 * (e - A.nax);
-      k0 = kk[0] == 0 && kk[1] == 0 && kk[2] == 0;
-      slot = A.slot_gen[e - A.nax];
-    }
-    A.skacc[slot] += k0 ? M * M / (double)N : (re * re + im * im) / (double)N;
+    R.skl[e] += (re * re + im * im) / (double)N;
   }
   __syncthreads();
 }
 
 template <int D, typename T>
-__device__ __forceinline__ void res_sample_corr(const ResArgs& A, const T* st, const double* tw, double* scr, int64_t sidx) {
+__device__ __forceinline__ void res_sample_corr(const ResArgs& A, const ResLocal& R, const T* st,
+                                                const double* tw, double* scr, int64_t sidx, int rpos) {
   constexpr int Q = 2 * D + 1;
   const int nx = A.nx, ny = A.ny, nz = A.nz, N = nx * ny * nz, nrows = ny * nz;
   const int nk = A.cnk;
@@ -273,13 +387,13 @@ __device__ __forceinline__ void res_sample_corr(const ResArgs& A, const T* st, c
   const int parts = res_parts(items, D == 1 ? 64 : (nrows < 64 ? nrows : 64));
   for (int t = threadIdx.x; t < items * parts; t += kResThreads) {
     const int kk = t / (Q * parts), i = (t / parts) % Q, p = t % parts;
-    const int kx = A.ckinfo[3 * kk], ky = A.ckinfo[3 * kk + 1], kz = A.ckinfo[3 * kk + 2];
+    const int4 kv = R.cki[kk];
     const T* fi = st + i * N;
     double re = 0, im = 0;
     int r0 = 0, r1 = nrows, rs = 1, x0 = 0, x1 = nx;
     if (D == 1) {
-      x0 = (int)((int64_t)nx * p / parts);
-      x1 = (int)((int64_t)nx * (p + 1) / parts);
+      x0 = nx * p / parts;
+      x1 = nx * (p + 1) / parts;
     } else {
       r0 = p;
       rs = parts;
@@ -287,8 +401,8 @@ __device__ __forceinline__ void res_sample_corr(const ResArgs& A, const T* st, c
     for (int r = r0; r < r1; r += rs) {
       const int y = r % ny, z = r / ny;
       double rc, rsn;  // twiddle of the row's y, z part
-      res_twiddle<D>(tw, nx, ny, nz, 0, ky, kz, 0, y, z, 1.0, rc, rsn);
-      int px = (int)(((int64_t)kx * x0) % nx);
+      res_twiddle<D>(tw, nx, ny, nz, 0, kv.y, kv.z, 0, y, z, 1.0, rc, rsn);
+      int px = (int)(((unsigned)kv.x * (unsigned)x0) % (unsigned)nx);
       const T* row = fi + r * nx;
       for (int x = x0; x < x1; ++x) {
         const double c = tw[2 * px] * rc - tw[2 * px + 1] * rsn;
@@ -296,13 +410,13 @@ __device__ __forceinline__ void res_sample_corr(const ResArgs& A, const T* st, c
         const double v = (double)row[x];
         re += v * c;
         im += v * s;
-        px += kx;
+        px += kv.x;
         if (px >= nx) px -= nx;
       }
     }
     if (parts == 1) {
-      A.amp[2 * t] = re;
-      A.amp[2 * t + 1] = im;
+      R.amp[2 * t] = re;
+      R.amp[2 * t + 1] = im;
     } else {
       scr[2 * t] = re;
       scr[2 * t + 1] = im;
@@ -316,36 +430,40 @@ __device__ __forceinline__ void res_sample_corr(const ResArgs& A, const T* st, c
         re += scr[2 * (u * parts + p)];
         im += scr[2 * (u * parts + p) + 1];
       }
-      A.amp[2 * u] = re;
-      A.amp[2 * u + 1] = im;
+      R.amp[2 * u] = re;
+      R.amp[2 * u + 1] = im;
     }
     __syncthreads();
   }
-  // S_ij, time correlator and ring (the arithmetic of k_corr_accumulate)
-  const int64_t ns = (int64_t)nk * Q * Q, nt = ns + (int64_t)nk * A.nlag;
-  for (int64_t t = threadIdx.x; t < nt; t += kResThreads) {
+  // S_ij, time correlator and ring (the arithmetic of k_corr_accumulate); a
+  // C entry with l >= 1 reads ring slot (sidx - l) mod nlag, never the slot
+  // rpos = sidx mod nlag written here.  Indices fit 32 bits (nk Q Q <= 50176,
+  // nk nlag <= 2^20).
+  const int nlag = A.nlag;
+  const int ns = nk * Q * Q, nt = ns + nk * nlag;
+  for (int t = threadIdx.x; t < nt; t += kResThreads) {
     if (t < ns) {
-      const int k = (int)(t / (Q * Q)), i = (int)((t / Q) % Q), j = (int)(t % Q);
-      const double* a = A.amp + (int64_t)k * 2 * Q;
+      const int k = t / (Q * Q), i = (t / Q) % Q, j = t % Q;
+      const double* a = R.amp + k * 2 * Q;
       const double ar = a[2 * i], ai = a[2 * i + 1], br = a[2 * j], bi = a[2 * j + 1];
-      A.sij[2 * t] += ar * br + ai * bi;
-      A.sij[2 * t + 1] += ai * br - ar * bi;
+      R.sij[2 * t] += ar * br + ai * bi;
+      R.sij[2 * t + 1] += ai * br - ar * bi;
       if (i == 0 && j == 0) {
         double rr = 0, ri = 0;
         for (int q = 0; q < Q; ++q) {
           rr += a[2 * q];
           ri += a[2 * q + 1];
         }
-        double* slot = A.ring + 2 * ((sidx % A.nlag) * (int64_t)nk + k);
+        double* slot = R.ring + 2 * (rpos * nk + k);
         slot[0] = rr;
         slot[1] = ri;
       }
       continue;
     }
-    const int64_t u = t - ns;
-    const int k = (int)(u / A.nlag), l = (int)(u % A.nlag);
+    const int u = t - ns;
+    const int k = u / nlag, l = u % nlag;
     if (l > sidx) continue;
-    const double* a = A.amp + (int64_t)k * 2 * Q;
+    const double* a = R.amp + k * 2 * Q;
     double rr = 0, ri = 0;
     for (int q = 0; q < Q; ++q) {
       rr += a[2 * q];
@@ -353,12 +471,13 @@ __device__ __forceinline__ void res_sample_corr(const ResArgs& A, const T* st, c
     }
     double pr = rr, pi = ri;
     if (l > 0) {
-      const double* old = A.ring + 2 * (((sidx - l) % A.nlag) * (int64_t)nk + k);
+      const int slot = rpos - l < 0 ? rpos - l + nlag : rpos - l;
+      const double* old = R.ring + 2 * (slot * nk + k);
       pr = old[0];
       pi = old[1];
     }
-    A.ct[2 * u] += pr * rr + pi * ri;
-    A.ct[2 * u + 1] += pi * rr - pr * ri;
+    R.ct[2 * u] += pr * rr + pi * ri;
+    R.ct[2 * u + 1] += pi * rr - pr * ri;
   }
   __syncthreads();
 }
@@ -370,13 +489,59 @@ __global__ void __launch_bounds__(kResThreads) k_resident(KParams<T> P, ResArgs 
   const int nx = A.nx, ny = A.ny, nz = A.nz;
   const int N = nx * ny * nz;
   const int lsum = nx + ny + nz;
+  const int ne = A.sk_every > 0 ? A.nax + A.ngen : 0;
+  const int cnk = A.corr_every > 0 ? A.cnk : 0;
   T* st = (T*)res_smem;
   double* rho = (double*)(res_smem + res_state_bytes((size_t)Q * N * sizeof(T)));
-  double* marg = rho + N;
-  double* tw = marg + lsum;
+  double* marg = rho + ((N + 1) & ~1);
+  double* tw = marg + ((lsum + 1) & ~1);
   double* scr = tw + 2 * lsum;
+  ResLocal R;
+  R.mom = scr + kResScratch;
+  R.skl = R.mom + kNV;
+  R.ent = (int4*)(R.skl + ((ne + 1) & ~1));
+  R.eslot = (int*)(R.ent + ne);
+  R.cki = (int4*)(R.eslot + ((ne + 3) & ~3));
+  const int nsij = 2 * Q * Q * cnk, nct = 2 * cnk * A.nlag;
+  if (A.corr_lds) {
+    R.amp = (double*)(R.cki + cnk);
+    R.sij = R.amp + 2 * Q * cnk;
+    R.ct = R.sij + nsij;
+    R.ring = R.ct + nct;
+  } else {
+    R.amp = A.amp;
+    R.sij = A.sij;
+    R.ct = A.ct;
+    R.ring = A.ring;
+  }
   const int tid = threadIdx.x;
   for (int m = tid; m < 2 * lsum; m += kResThreads) tw[m] = A.tw[m];
+  for (int v = tid; v < kNV; v += kResThreads) R.mom[v] = 0.0;
+  for (int e = tid; e < ne; e += kResThreads) {
+    R.skl[e] = 0.0;
+    int4 en;
+    if (e < A.nax) {
+      const int a = (int)A.kinfo[2 * e], k = (int)A.kinfo[2 * e + 1];
+      en = make_int4(a, a == 0 ? k : 0, a == 1 ? k : 0, a == 2 ? k : 0);
+      R.eslot[e] = A.slot_ax[e];
+    } else {
+      const int64_t* kk = A.kv + 3 * (e - A.nax);
+      const int nnz = (kk[0] != 0) + (kk[1] != 0) + (kk[2] != 0);
+      const int a = nnz == 0 ? -1 : (nnz > 1 ? -2 : (kk[0] != 0 ? 0 : (kk[1] != 0 ? 1 : 2)));
+      en = make_int4(a, (int)kk[0], (int)kk[1], (int)kk[2]);
+      R.eslot[e] = A.slot_gen[e - A.nax];
+    }
+    R.ent[e] = en;
+  }
+  for (int k = tid; k < cnk; k += kResThreads)
+    R.cki[k] = make_int4(A.ckinfo[3 * k], A.ckinfo[3 * k + 1], A.ckinfo[3 * k + 2], 0);
+  if (A.corr_lds) {
+    for (int m = tid; m < nsij; m += kResThreads) R.sij[m] = A.sij[m];
+    for (int m = tid; m < nct; m += kResThreads) {
+      R.ct[m] = A.ct[m];
+      R.ring[m] = A.ring[m];
+    }
+  }
   // canonical state f_i(x) = g_i(x - v_i); coordinates of this thread's sites
   const T* g = (const T*)A.gin;
   int sites[SPT], cx[SPT], cy[SPT], cz[SPT];
@@ -396,13 +561,32 @@ __global__ void __launch_bounds__(kResThreads) k_resident(KParams<T> P, ResArgs 
     }
   }
   __syncthreads();
+  // steps until the next sample of each kind (0: this step), counted down
+  // instead of a 64-bit modulo per step
+  int64_t cm = A.mom_every > 0 ? (A.mom_every - A.step0 % A.mom_every) % A.mom_every : -1;
+  int64_t cc = cnk > 0 ? (A.corr_every - A.step0 % A.corr_every) % A.corr_every : -1;
+  int64_t cs = ne > 0 ? (A.sk_every - A.step0 % A.sk_every) % A.sk_every : -1;
   int64_t csamp = A.corr_s0;
+  int rpos = cnk > 0 ? (int)(A.corr_s0 % A.nlag) : 0;
   T* out = (T*)A.gout;
   for (int k = 0; k < A.nsteps; ++k) {
     const int64_t t = A.step0 + k;
-    if (A.mom_every > 0 && t % A.mom_every == 0) res_sample_moments<D, T, SPT>(st, N, scr, A.momacc, sites);
-    if (A.corr_every > 0 && t % A.corr_every == 0) res_sample_corr<D, T>(A, st, tw, scr, csamp++);
-    if (A.sk_every > 0 && t % A.sk_every == 0) res_sample_sk<D, T, SPT>(A, st, rho, marg, tw, scr, sites);
+    if (cm == 0) {
+      res_sample_moments<D, T, SPT>(st, N, scr, R.mom, sites);
+      cm = A.mom_every;
+    }
+    if (cc == 0) {
+      res_sample_corr<D, T>(A, R, st, tw, scr, csamp++, rpos);
+      rpos = rpos + 1 == A.nlag ? 0 : rpos + 1;
+      cc = A.corr_every;
+    }
+    if (cs == 0) {
+      res_sample_sk<D, T, SPT>(A, R, st, rho, marg, tw, scr, sites);
+      cs = A.sk_every;
+    }
+    --cm;
+    --cc;
+    --cs;
     const uint32_t t32 = (uint32_t)((uint64_t)t & 0xFFFFFFFFull);
     T f[SPT][Q];
 #pragma unroll
@@ -444,6 +628,17 @@ __global__ void __launch_bounds__(kResThreads) k_resident(KParams<T> P, ResArgs 
       }
     }
     __syncthreads();
+  }
+  // flush this launch's sums
+  if (A.mom_every > 0)
+    for (int v = tid; v < kNV; v += kResThreads) A.momacc[v] += R.mom[v];
+  for (int e = tid; e < ne; e += kResThreads) A.skacc[R.eslot[e]] += R.skl[e];
+  if (A.corr_lds) {
+    for (int m = tid; m < nsij; m += kResThreads) A.sij[m] = R.sij[m];
+    for (int m = tid; m < nct; m += kResThreads) {
+      A.ct[m] = R.ct[m];
+      A.ring[m] = R.ring[m];
+    }
   }
 }
 

@@ -22,17 +22,21 @@ DEFAULTS = {1: dict(kernel="rows", tile_x=256, tile_rows=1, nt_store=0),
             2: dict(kernel="rows", tile_x=256, tile_rows=4, nt_store=0),
             3: dict(kernel="rows", tile_x=256, tile_rows=4, nt_store=0)}
 
-CANDIDATES = ([("plain", 0, 0, 0, 0)] +
+CANDIDATES = ([("plain", 0, 0, 0, 0), ("resident", 0, 0, 0, 0)] +
               [("flat", 0, ry, nt, 0) for ry in (1, 2, 4, 8) for nt in (0, 1)] +
               [("rows", tx, ry, nt, 0) for tx in (64, 128, 256, 512, 1024) for ry in (1, 2, 4, 8, 16)
                for nt in (0, 1)] +
               [("rows", tx, ry, nt, 1) for tx in (128, 256, 512) for ry in (2, 4, 8, 16) for nt in (0, 1)])
-QUICK = ([("plain", 0, 0, 0, 0)] + [("flat", 0, ry, nt, 0) for ry in (1, 2, 4) for nt in (0, 1)] +
+QUICK = ([("plain", 0, 0, 0, 0), ("resident", 0, 0, 0, 0)] +
+         [("flat", 0, ry, nt, 0) for ry in (1, 2, 4) for nt in (0, 1)] +
          [("rows", tx, ry, 1, 0) for tx in (256, 512) for ry in (1, 2, 4)])
 
 
 def size_class(dims):
+    """tiny lattices (up to 4096 sites) may be resident in one workgroup's LDS"""
     n = int(np.prod(dims))
+    if n <= 4096:
+        return "tiny"
     return "small" if n < (1 << 16) else ("medium" if n < (1 << 22) else "large")
 
 
@@ -52,6 +56,8 @@ def best_config(d, precision, dims):
     """Kernel keyword arguments for a lattice: the cached tuning result, or
     the defaults."""
     ent = _load().get(_key(d, precision, dims))
+    if size_class(dims) == "tiny" and (not ent or ent["kernel"] == "resident"):
+        return dict(kernel="auto")      # resident when the lattice fits the LDS, else rows
     if ent:
         return dict(kernel=ent["kernel"], tile_x=ent["tile_x"], tile_rows=ent["tile_rows"],
                     nt_store=ent.get("nt_store", 0), pipeline=ent.get("pipeline", 0))
@@ -75,8 +81,11 @@ def tune(d, precision, dims, steps=100, candidates=None, write=True, verbose=Tru
         pp = cand[4] if len(cand) > 4 else 0
         if d == 1 and ry > 1:
             continue
-        L = flb.Lattice(d, dims, precision=precision, omega=1.0, seed=0, kernel=kern, tile_x=tx,
-                        tile_rows=ry, nt_store=nt, pipeline=pp)
+        try:
+            L = flb.Lattice(d, dims, precision=precision, omega=1.0, seed=0, kernel=kern, tile_x=tx,
+                            tile_rows=ry, nt_store=nt, pipeline=pp)
+        except flb.FlbError:          # the resident kernel on a lattice that does not fit
+            continue
         L.set_populations(f0)
         L.step(3)
         state = L.get_populations()

@@ -57,8 +57,10 @@ def test_resident_noise_modes(noise, law):
 
 
 @pytest.mark.parametrize("precision", [8, 4])
-@pytest.mark.parametrize("d,dims", [(1, (256,)), (2, (37, 23)), (3, (12, 10, 9))])
+@pytest.mark.parametrize("d,dims", [(1, (256,)), (1, (1000,)), (2, (37, 23)), (2, (32, 16)), (3, (12, 10, 9)),
+                                    (3, (8, 4, 16))])
 def test_resident_sampling_equals_hbm_path(d, dims, precision):
+    # power-of-two axes take the FFT of the marginal, the others a DFT
     a = _run(d, dims, precision, "resident", 23, t0=1, sample=True)
     b = _run(d, dims, precision, "flat", 23, t0=1, sample=True)
     assert np.array_equal(a["f"], b["f"])
