@@ -233,6 +233,16 @@ int flb_correlation(flb_lattice* h, double* sij, double* ct, int64_t* nsamples);
  * doubles, index (k Q + i).  Synchronises the stream. */
 int flb_fourier_amplitudes(flb_lattice* h, double* amp);
 
+/* Density profile along one axis (Sec. IV, non-equilibrium dynamics: the
+ * diffusion front is averaged over the other directions, and its variance
+ * compared with eq. rhoth).  For every coordinate c along `axis` (0 = x,
+ * 1 = y, 2 = z; below the model's dimension), sum_rho[c] and sum_rho2[c] are
+ * the FP64 sums of rho and rho^2 over the sites with that coordinate, for
+ * the current state, in a fixed order.  Host arrays of n[axis] doubles.
+ * The library allocates its device buffers on the first call (freed by
+ * flb_destroy).  Synchronises the stream. */
+int flb_profile(flb_lattice* h, int32_t axis, double* sum_rho, double* sum_rho2);
+
 /* Block until the handle's stream has finished. */
 int flb_sync(flb_lattice* h);
 

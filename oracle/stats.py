@@ -148,3 +148,17 @@ def correlate(f0, p, nsteps, kvecs, every, nlag, t0=0, rho_eq=None):
                 ct[:, l] += history[s - l] * np.conj(r)
         f = run(f, p, 1, t0=t, rho_eq=rho_eq, lat=lat)
     return {"sij": sij, "ct": ct, "nsamples": len(history), "f": f}
+
+
+def profile(f, axis=0):
+    """Density profile along one axis (Sec. IV, non-equilibrium dynamics: the
+    front is averaged over the other directions): for every coordinate c
+    along `axis` (0 = x, 1 = y, 2 = z), the sums over all sites with that
+    coordinate of rho and of rho^2.  Returns (sum_rho, sum_rho2), each of the
+    axis' length."""
+    f = np.asarray(f, dtype=np.float64)
+    rho = f.sum(axis=0)                    # index order (.., y, x)
+    d = rho.ndim
+    keep = d - 1 - axis                    # array axis of the requested lattice axis
+    others = tuple(a for a in range(d) if a != keep)
+    return rho.sum(axis=others), (rho * rho).sum(axis=others)

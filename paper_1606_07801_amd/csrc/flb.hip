@@ -401,6 +401,23 @@ void launch_resident(flb_lattice* h, int c, size_t lds, int corr_lds) {
   h->step += c;
 }
 
+// density profile along `axis` into out (sums of rho, then of rho^2)
+template <int D, typename T>
+void launch_profile_t(flb_lattice* h, int axis, double* part, double* out) {
+  const T* g = (const T*)lat_buffer(h, h->cur);
+  const int64_t nx = h->p.n[0], ny = h->p.n[1], nz = h->p.n[2], nrows = ny * nz;
+  if (axis == 0) {
+    const int64_t nchunk = std::min<int64_t>(kColChunks, nrows), rpc = (nrows + nchunk - 1) / nchunk;
+    k_prof_cols<D, T><<<dim3((unsigned)((nx + 255) / 256), (unsigned)nchunk), 256, 0, h->stream>>>(g, nx, ny, nz, rpc,
+                                                                                                    part);
+    k_prof_cols_final<<<(unsigned)((nx + 255) / 256), 256, 0, h->stream>>>(part, nchunk, nx, out);
+  } else {
+    k_prof_rows<D, T><<<(unsigned)nrows, 256, 0, h->stream>>>(g, nx, ny, nz, part);
+    const int64_t L = h->p.n[axis];
+    k_prof_yz<<<(unsigned)((L + 255) / 256), 256, 0, h->stream>>>(part, ny, nz, axis, out);
+  }
+}
+
 // population correlators: Fourier sums of the current state, then one
 // accumulation step (S_ij, time correlator, ring of rho(k))
 template <int D, typename T>
@@ -736,6 +753,7 @@ int flb_create(const flb_params* p, void* d_pop, size_t pop_bytes, void* d_work,
   h->corr_nk = h->corr_nlag = h->corr_nsb = 0;
   h->corr_count = 0;
   h->corr_mem = nullptr;
+  h->prof_mem = nullptr;
   {  // twiddle tables of the structure factor and of the resident kernel
     double* tw = (double*)(h->work + h->wl.tw);
     const int64_t L3[3] = {p->n[0], p->n[1], p->n[2]};
@@ -762,6 +780,7 @@ int flb_destroy(flb_lattice* h) {
   (void)hipStreamSynchronize(h->stream);
   if (h->own_work) (void)hipFree(h->work);
   if (h->corr_mem) (void)hipFree(h->corr_mem);
+  if (h->prof_mem) (void)hipFree(h->prof_mem);
   (void)hipHostFree(h->stage);
   delete h;
   return FLB_OK;
@@ -1065,6 +1084,40 @@ int flb_fourier_amplitudes(flb_lattice* h, double* amp) {
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(amp, h->corr_mem + h->corr_off[3], sizeof(double) * 2 * h->Q * (size_t)h->corr_nk,
                          hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return FLB_OK;
+}
+
+
+int flb_profile(flb_lattice* h, int32_t axis, double* sum_rho, double* sum_rho2) {
+  if (!h || !sum_rho || !sum_rho2) return fail(FLB_EINVAL, "NULL argument");
+  if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
+  if (axis < 0 || axis >= h->d) return fail(FLB_EINVAL, "axis %d outside [0, %d)", axis, h->d);
+  DeviceGuard g(h->device);
+  const int64_t nx = h->p.n[0], ny = h->p.n[1], nz = h->p.n[2], nrows = ny * nz;
+  const int64_t L = h->p.n[axis];
+  const size_t part_d = std::max<size_t>(2 * (size_t)std::min<int64_t>(kColChunks, nrows) * nx, 2 * (size_t)nrows);
+  const size_t bytes = sizeof(double) * (part_d + 2 * (size_t)std::max(nx, std::max(ny, nz)));
+  if (!h->prof_mem) {
+    void* mem = nullptr;
+    const hipError_t e = hipMalloc(&mem, bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc (profile buffers)");
+    h->prof_mem = (char*)mem;
+  }
+  double* part = (double*)h->prof_mem;
+  double* out = part + part_d;
+  if (h->s == 4) {
+    if (h->d == 1) launch_profile_t<1, float>(h, axis, part, out);
+    else if (h->d == 2) launch_profile_t<2, float>(h, axis, part, out);
+    else launch_profile_t<3, float>(h, axis, part, out);
+  } else {
+    if (h->d == 1) launch_profile_t<1, double>(h, axis, part, out);
+    else if (h->d == 2) launch_profile_t<2, double>(h, axis, part, out);
+    else launch_profile_t<3, double>(h, axis, part, out);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(sum_rho, out, sizeof(double) * L, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipMemcpyAsync(sum_rho2, out + L, sizeof(double) * L, hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   return FLB_OK;
 }

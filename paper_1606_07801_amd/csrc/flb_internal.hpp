@@ -83,6 +83,7 @@ struct flb_lattice {
   bool resident;
   size_t res_lds;        // its LDS bytes
   int res_lds_max;       // the device's LDS bytes per workgroup
+  char* prof_mem;        // density-profile buffers (library-allocated on first use)
 };
 
 namespace flb {

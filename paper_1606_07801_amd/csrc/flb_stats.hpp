@@ -329,6 +329,78 @@ __global__ void k_sk_direct_final(const double* __restrict__ partial, int64_t nc
   }
 }
 
+// ---------------------------------------------------------------------------
+// Density profile along one axis: for every coordinate, the sums of rho and
+// rho^2 over the sites with that coordinate, in a fixed order.
+// x: chunk c of the rows gives part[(c * nx + x) * 2 + {0, 1}].
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_prof_cols(const T* __restrict__ g, int64_t nx, int64_t ny,
+                                                   int64_t nz, int64_t rpc, double* __restrict__ part) {
+  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (x >= nx) return;
+  const int64_t n = nx * ny * nz, nrows = ny * nz;
+  const int64_t c = blockIdx.y, r0 = c * rpc, r1 = r0 + rpc < nrows ? r0 + rpc : nrows;
+  double s = 0, s2 = 0;
+  for (int64_t r = r0; r < r1; ++r) {
+    const double rho = site_density<D, T>(g, n, x, r % ny, r / ny, nx, ny, nz);
+    s += rho;
+    s2 += rho * rho;
+  }
+  part[(c * nx + x) * 2] = s;
+  part[(c * nx + x) * 2 + 1] = s2;
+}
+
+// out[x] = sum over chunks (in order) of part, out[nx + x] the same for rho^2
+__global__ void k_prof_cols_final(const double* __restrict__ part, int64_t nchunk, int64_t nx,
+                                  double* __restrict__ out) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nx) return;
+  double s = 0, s2 = 0;
+  for (int64_t c = 0; c < nchunk; ++c) {
+    s += part[(c * nx + x) * 2];
+    s2 += part[(c * nx + x) * 2 + 1];
+  }
+  out[x] = s;
+  out[nx + x] = s2;
+}
+
+// y / z: one block per row r = y + ny z sums rho and rho^2 over x into rs[2 r + {0, 1}]
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_prof_rows(const T* __restrict__ g, int64_t nx, int64_t ny,
+                                                   int64_t nz, double* __restrict__ rs) {
+  __shared__ double lds[4];
+  const int64_t r = blockIdx.x, n = nx * ny * nz;
+  double s = 0, s2 = 0;
+  for (int64_t x = threadIdx.x; x < nx; x += blockDim.x) {
+    const double rho = site_density<D, T>(g, n, x, r % ny, r / ny, nx, ny, nz);
+    s += rho;
+    s2 += rho * rho;
+  }
+  s = block_sum256(s, lds);
+  __syncthreads();
+  s2 = block_sum256(s2, lds);
+  if (threadIdx.x == 0) {
+    rs[2 * r] = s;
+    rs[2 * r + 1] = s2;
+  }
+}
+
+// out[c] (and out[L + c] for rho^2) for c along y (axis 1) or z (axis 2)
+__global__ void k_prof_yz(const double* __restrict__ rs, int64_t ny, int64_t nz, int axis,
+                          double* __restrict__ out) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t L = axis == 1 ? ny : nz, M = axis == 1 ? nz : ny;
+  if (c >= L) return;
+  double s = 0, s2 = 0;
+  for (int64_t o = 0; o < M; ++o) {
+    const int64_t r = axis == 1 ? c + ny * o : o + ny * c;
+    s += rs[2 * r];
+    s2 += rs[2 * r + 1];
+  }
+  out[c] = s;
+  out[L + c] = s2;
+}
+
 __global__ void k_add(const double* __restrict__ v, double* __restrict__ acc, int n) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < n) acc[j] += v[j];

@@ -27,7 +27,7 @@ EXPORTS = (
     "flb_create", "flb_set_populations", "flb_get_populations", "flb_step",
     "flb_get_step", "flb_moments", "flb_structure_factor", "flb_set_sampling",
     "flb_set_moment_sampling", "flb_sampled_moments", "flb_set_correlation",
-    "flb_correlation", "flb_fourier_amplitudes", "flb_sync", "flb_destroy",
+    "flb_correlation", "flb_fourier_amplitudes", "flb_profile", "flb_sync", "flb_destroy",
     "flb_noise_sample", "flb_batch_create", "flb_batch_admit", "flb_batch_retire",
     "flb_batch_step", "flb_batch_size", "flb_batch_sync", "flb_batch_destroy",
 )
@@ -109,6 +109,7 @@ def load(path=LIB_PATH):
         "flb_set_correlation": ([vp, i64, vp, i32, i32], ctypes.c_int),
         "flb_correlation": ([vp, dp, dp, ctypes.POINTER(i64)], ctypes.c_int),
         "flb_fourier_amplitudes": ([vp, dp], ctypes.c_int),
+        "flb_profile": ([vp, i32, dp, dp], ctypes.c_int),
         "flb_sync": ([vp], ctypes.c_int),
         "flb_destroy": ([vp], ctypes.c_int),
         "flb_noise_sample": ([i32, i32, i32, u64, i64, i64, i64, vp, vp, vp], ctypes.c_int),
@@ -303,6 +304,13 @@ class Lattice:
         a = np.zeros((nk, self.Q, 2))
         check(load().flb_fourier_amplitudes(self.handle, a.ctypes.data))
         return a[..., 0] + 1j * a[..., 1]
+
+    def profile(self, axis=0):
+        """(sum of rho, sum of rho^2) over the sites of each coordinate along `axis`."""
+        L = self.dims[axis]
+        s, s2 = np.zeros(L), np.zeros(L)
+        check(load().flb_profile(self.handle, int(axis), s.ctypes.data, s2.ctypes.data))
+        return s, s2
 
     def _moments_dict(self, m):
         Q = self.Q

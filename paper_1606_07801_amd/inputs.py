@@ -111,3 +111,15 @@ def request_stream(n, rate, seed=0, sites=(1e3, 1e8), steps=(1e2, 1e5),
         out.append({"id": r, "arrival": t, "d": d, "dims": (side,) * d,
                     "steps": nsteps, "omega": om, "rho": rm, "seed": r})
     return out
+
+
+def block_profile(nx, rho_in, rho_out):
+    """Density rho_in on [nx/4, 3nx/4), rho_out elsewhere (the step initial
+    condition of a diffusion front on a periodic line)."""
+    x = np.arange(nx)
+    return np.where((x >= nx // 4) & (x < 3 * nx // 4), rho_in, rho_out).astype(np.float64)
+
+
+def poisson_sites(lam, seed=0):
+    """Independent Poisson counts with a mean per entry of lam (any shape)."""
+    return rng(seed).poisson(np.asarray(lam, dtype=np.float64)).astype(np.float64)

@@ -253,3 +253,22 @@ def test_poisson_initial_counts_table2(golden_dir):
         emp = (counts.mean(), (counts ** 2).mean(), (counts ** 3).mean())
         for e, m in zip(emp, mom):
             assert abs(e / m - 1) < 0.02
+
+
+@pytest.mark.parametrize("shape", [(7,), (4, 6), (3, 4, 5)])
+def test_profile_brute_force(shape):
+    # sums of rho and rho^2 over the sites of each coordinate, by explicit loops
+    gen = np.random.default_rng(11)
+    d = len(shape)
+    Q = 2 * d + 1
+    f = gen.normal(1.0, 2.0, size=(Q,) + tuple(reversed(shape)))
+    rho = f.sum(axis=0)
+    for axis in range(d):
+        s, s2 = oracle.profile(f, axis)
+        ref, ref2 = np.zeros(shape[axis]), np.zeros(shape[axis])
+        for idx in np.ndindex(*rho.shape):
+            c = idx[d - 1 - axis]              # array index order is (.., y, x)
+            ref[c] += rho[idx]
+            ref2[c] += rho[idx] ** 2
+        assert np.allclose(s, ref, rtol=1e-13, atol=1e-12)
+        assert np.allclose(s2, ref2, rtol=1e-13, atol=1e-12)

@@ -305,3 +305,21 @@ def test_run_sites_matches_full_run(d, T):
         for n, c in enumerate(coords):
             idx = tuple(int(c[a]) for a in reversed(range(d)))
             assert np.abs(g[(slice(None),) + idx] - vals[:, n]).max() < 1e-12
+
+
+def test_noise_off_front_follows_the_erf_solution():
+    # Sec. IV, non-equilibrium dynamics: at unit rates (D = theta / 2) the
+    # deterministic block profile of a y-uniform D2Q5 strip approaches the
+    # continuum erf solution as the front widens
+    lat = oracle.make_lattice(2)
+    x = np.arange(100)
+    rho0 = np.where((x >= 25) & (x < 75), 20.0, 120.0)
+    f = lat.w[:, None, None] * rho0[None, None, :]
+    p = oracle.Params(d=2, omega_j=1.0, noise="off")
+    prev, errs = 0, []
+    for t in (100, 400, 1600):
+        f = oracle.run(f, p, t - prev, t0=prev)
+        prev = t
+        errs.append(np.abs(f.sum(axis=0)[0] - cf.front_profile(100, t, lat.theta / 2, 20.0, 120.0)).max())
+    assert errs[0] < 0.05 and errs[1] < 0.01 and errs[2] < 0.005
+    assert errs[2] < errs[1] < errs[0]
