@@ -21,7 +21,9 @@ philox   Philox4x32-10 counter-based generator (Salmon et al., SC'11) and the
          mapping of its words to uniform and Gaussian variates
 step     one collision + streaming step: eq. (LB), eq. (collision) with the
          moment-space relaxation and the local / global noise variance
-         eq. (xilocal) / eq. (xiglobal), negative-density rule of Sec. IV
+         eq. (xilocal) / eq. (xiglobal), negative-density rule of Sec. IV;
+         lattices whose theta and rates vary by region (Sec. IV,
+         non-homogeneous systems)
 stats    lattice sums (mass, <f_i>, <f_i f_j>), the density structure
          factor S(k), the populations' Fourier sums, their structure factor
          S_ij(k) and the density time correlator (Sec. IV)
@@ -32,6 +34,7 @@ an independent pin say "parity unpinned".
 
 from .lattice import Lattice, make_lattice  # noqa: F401
 from .philox import philox4x32_10, words_to_uniform, box_muller  # noqa: F401
-from .step import Params, collide, stream, step, run, noise_draws, step_sites, run_sites  # noqa: F401
+from .step import (Params, collide, stream, step, run, noise_draws, step_sites, run_sites,  # noqa: F401
+                   step_regions, run_regions)
 from .stats import (lattice_sums, structure_factor, density, population_amplitudes, correlate,  # noqa: F401
                     profile)

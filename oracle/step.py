@@ -255,3 +255,35 @@ def run_sites(f0, lat, p, t0, nsteps, coords, rho_eq=None, horizon=0):
     if horizon:
         return W[centre], minrho
     return W[centre]
+
+
+def step_regions(f, plist, region, t, rho_eq=None):
+    """One step of a lattice whose temperature and rates vary in space (Sec. IV,
+    non-homogeneous systems): the sites with region[x] == r collide with the
+    weights and basis of plist[r].theta and the rates of plist[r] (eq. f0def
+    with the local theta, eq. collision), then all populations stream
+    (eq. LB; the velocity set does not depend on theta).  region has the
+    lattice's shape (.., y, x); every plist entry has the same d, seed, noise
+    and law."""
+    Q = f.shape[0]
+    dims = _dims(f)
+    nsite = int(np.prod(dims))
+    flat = np.asarray(f, dtype=np.float64).reshape(Q, nsite)
+    reg = np.asarray(region).reshape(nsite)
+    fstar = np.empty_like(flat)
+    lats = [p.lattice() for p in plist]
+    for r, p in enumerate(plist):
+        idx = np.flatnonzero(reg == r)
+        if idx.size:
+            fstar[:, idx] = collide(flat[:, idx], idx.astype(np.uint64), lats[r], p, t, rho_eq)
+    return stream(fstar.reshape((Q,) + dims), lats[0])
+
+
+def run_regions(f, plist, region, nsteps, t0=0, rho_eq=None):
+    """nsteps of step_regions from step index t0 (global noise: rho^eq from
+    the initial state unless given)."""
+    if plist[0].noise == "global" and rho_eq is None:
+        rho_eq = mean_density(f)
+    for t in range(t0, t0 + nsteps):
+        f = step_regions(f, plist, region, t, rho_eq)
+    return f
