@@ -233,6 +233,22 @@ int flb_correlation(flb_lattice* h, double* sij, double* ct, int64_t* nsamples);
  * doubles, index (k Q + i).  Synchronises the stream. */
 int flb_fourier_amplitudes(flb_lattice* h, double* amp);
 
+/* Temperature and rates varying in space (Sec. IV, non-homogeneous systems:
+ * two domains of different theta, or of different current relaxation time
+ * and hence diffusion constant).  region (host, n[0] n[1] n[2] bytes, x
+ * fastest) gives every site's region r < nregions <= 16; theta[r] (each in
+ * (0, 1/d); 0 is not allowed here) and omega[3 r .. 3 r + 2] (omega_j,
+ * omega_n, omega_s as in flb_params, 0 for n and s meaning omega_j) set the
+ * equilibrium weights, moment basis and rates with which that site collides
+ * (eq. f0def with the local theta, eq. collision); streaming is unchanged.
+ * The lattice's own theta and omega are then unused; seed, noise mode and
+ * law still apply.  nregions = 0 returns to the uniform lattice (region may
+ * be NULL).  Copies the map to library-allocated device memory (freed by
+ * flb_destroy); synchronises.  Stepping uses a per-site kernel; a lattice
+ * with regions cannot join a batch (FLB_EINVAL). */
+int flb_set_regions(flb_lattice* h, const uint8_t* region, int32_t nregions, const double* theta,
+                    const double* omega);
+
 /* Density profile along one axis (Sec. IV, non-equilibrium dynamics: the
  * diffusion front is averaged over the other directions, and its variance
  * compared with eq. rhoth).  For every coordinate c along `axis` (0 = x,

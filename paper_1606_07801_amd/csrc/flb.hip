@@ -176,6 +176,11 @@ char* lat_buffer(flb_lattice* h, int which) { return h->pop + (size_t)which * h-
 // step launch
 template <int D, typename T>
 int launch_step_t(flb_lattice* h, const T* g, T* out, uint32_t step, hipStream_t st) {
+  if (h->reg_n > 0) {
+    k_step_regions<D, T><<<(unsigned)((h->n + 255) / 256), 256, 0, st>>>(
+        g, out, (const KParams<T>*)h->reg_tab, h->reg_n, h->reg_map, h->n, step);
+    return 0;
+  }
   const KParams<T> P = make_kparams<T>(h->p, h->rho_eq);
   const int kern = h->p.kernel == FLB_KERNEL_AUTO ? FLB_KERNEL_ROWS : h->p.kernel;
   if (kern == FLB_KERNEL_PLAIN) {
@@ -284,6 +289,24 @@ void launch_moments(flb_lattice* h) {
     else launch_moments_t<3, double>(h, (const double*)g);
   }
 }
+
+// kernel constants of every region (theta, rates, the lattice's noise set-up
+// and global-noise density) into the device table; synchronous
+template <typename T>
+int rebuild_regions_t(flb_lattice* h) {
+  KParams<T> tab[kMaxRegions];
+  for (int r = 0; r < h->reg_n; ++r) {
+    flb_params q = h->p;
+    q.theta = h->reg_theta[r];
+    for (int a = 0; a < 3; ++a) q.omega[a] = h->reg_omega[r][a];
+    tab[r] = make_kparams<T>(q, h->rho_eq);
+  }
+  HIP_TRY(hipMemcpyAsync(h->reg_tab, tab, sizeof(KParams<T>) * h->reg_n, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return FLB_OK;
+}
+
+int rebuild_regions(flb_lattice* h) { return h->s == 4 ? rebuild_regions_t<float>(h) : rebuild_regions_t<double>(h); }
 
 // resident small lattice: `c` steps in one launch, sampling inside
 int64_t multiples_in(int64_t t0, int64_t c, int64_t every) {
@@ -754,6 +777,9 @@ int flb_create(const flb_params* p, void* d_pop, size_t pop_bytes, void* d_work,
   h->corr_count = 0;
   h->corr_mem = nullptr;
   h->prof_mem = nullptr;
+  h->reg_n = 0;
+  h->reg_map = nullptr;
+  h->reg_tab = nullptr;
   {  // twiddle tables of the structure factor and of the resident kernel
     double* tw = (double*)(h->work + h->wl.tw);
     const int64_t L3[3] = {p->n[0], p->n[1], p->n[2]};
@@ -781,6 +807,8 @@ int flb_destroy(flb_lattice* h) {
   if (h->own_work) (void)hipFree(h->work);
   if (h->corr_mem) (void)hipFree(h->corr_mem);
   if (h->prof_mem) (void)hipFree(h->prof_mem);
+  if (h->reg_map) (void)hipFree(h->reg_map);
+  if (h->reg_tab) (void)hipFree(h->reg_tab);
   (void)hipHostFree(h->stage);
   delete h;
   return FLB_OK;
@@ -804,6 +832,10 @@ int flb_set_populations(flb_lattice* h, const void* src, int src_on_device, int6
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->mass0 = h->stage->red[0];
   h->rho_eq = h->mass0 / (double)h->n;
+  if (h->reg_n > 0) {
+    const int rc = rebuild_regions(h);
+    if (rc) return rc;
+  }
   h->step = step;
   return FLB_OK;
 }
@@ -828,7 +860,7 @@ int flb_step(flb_lattice* h, int64_t nsteps) {
   DeviceGuard g(h->device);
   size_t lds = 0;
   int corr_lds = 0;
-  if (h->resident && resident_lds(h, &lds, &corr_lds)) {
+  if (h->resident && h->reg_n == 0 && resident_lds(h, &lds, &corr_lds)) {
     for (int64_t k = 0; k < nsteps;) {
       const int c = (int)std::min<int64_t>(nsteps - k, kResMaxChunk);
       launch_resident(h, c, lds, corr_lds);
@@ -847,7 +879,7 @@ int flb_step(flb_lattice* h, int64_t nsteps) {
     }
     if (h->corr_every > 0 && h->step % h->corr_every == 0) corr_sample(h);  // state before this step
     const bool sample = h->sample_every > 0 && h->step % h->sample_every == 0;
-    if (sample && h->sample_fused) {
+    if (sample && h->sample_fused && h->reg_n == 0) {
       launch_step_sampled(h, lat_buffer(h, h->cur), lat_buffer(h, nxt), t32);
       launch_sk(h, 1, true);
       sk_accumulate(h);
@@ -1088,6 +1120,47 @@ int flb_fourier_amplitudes(flb_lattice* h, double* amp) {
   return FLB_OK;
 }
 
+
+int flb_set_regions(flb_lattice* h, const uint8_t* region, int32_t nregions, const double* theta,
+                    const double* omega) {
+  if (!h) return fail(FLB_EINVAL, "NULL handle");
+  if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
+  DeviceGuard g(h->device);
+  if (nregions == 0) {
+    h->reg_n = 0;
+    return FLB_OK;
+  }
+  if (!region || !theta || !omega) return fail(FLB_EINVAL, "NULL argument");
+  if (nregions < 1 || nregions > kMaxRegions) return fail(FLB_EINVAL, "need 1 <= nregions <= %d", kMaxRegions);
+  for (int r = 0; r < nregions; ++r) {
+    if (!(theta[r] > 0.0 && theta[r] < 1.0 / h->d))
+      return fail(FLB_EINVAL, "region %d: theta = %g outside (0, 1/%d)", r, theta[r], h->d);
+    if (!(omega[3 * r] > 0.0 && omega[3 * r] < 2.0))
+      return fail(FLB_EINVAL, "region %d: omega_j = %g outside (0, 2)", r, omega[3 * r]);
+    for (int a = 1; a < 3; ++a)
+      if (omega[3 * r + a] != 0.0 && !(omega[3 * r + a] > 0.0 && omega[3 * r + a] < 2.0))
+        return fail(FLB_EINVAL, "region %d: omega[%d] = %g outside (0, 2)", r, a, omega[3 * r + a]);
+  }
+  for (int64_t s = 0; s < h->n; ++s)
+    if (region[s] >= nregions) return fail(FLB_EINVAL, "site %lld has region %d >= %d", (long long)s, region[s], nregions);
+  if (!h->reg_map) {
+    void* m = nullptr;
+    hipError_t e = hipMalloc(&m, (size_t)h->n);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc (region map)");
+    h->reg_map = (uint8_t*)m;
+    e = hipMalloc(&m, sizeof(KParams<double>) * kMaxRegions);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc (region table)");
+    h->reg_tab = (char*)m;
+  }
+  HIP_TRY(hipMemcpyAsync(h->reg_map, region, (size_t)h->n, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  for (int r = 0; r < nregions; ++r) {
+    h->reg_theta[r] = theta[r];
+    for (int a = 0; a < 3; ++a) h->reg_omega[r][a] = omega[3 * r + a];
+  }
+  h->reg_n = nregions;
+  return rebuild_regions(h);
+}
 
 int flb_profile(flb_lattice* h, int32_t axis, double* sum_rho, double* sum_rho2) {
   if (!h || !sum_rho || !sum_rho2) return fail(FLB_EINVAL, "NULL argument");

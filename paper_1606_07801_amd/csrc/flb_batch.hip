@@ -412,6 +412,7 @@ int flb_batch_admit(flb_batch* b, flb_lattice* h) {
   if (!b || !h) return fail(FLB_EINVAL, "NULL argument");
   if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is already in a batch");
   if (h->device != b->device) return fail(FLB_EINVAL, "lattice and batch are on different devices");
+  if (h->reg_n > 0) return fail(FLB_EINVAL, "a lattice with regions (flb_set_regions) is stepped alone");
   if (b->precision && (int)h->s != b->precision)
     return fail(FLB_EINVAL, "batch holds precision %d, lattice has %d", b->precision, (int)h->s);
   DevGuard g(b->device);

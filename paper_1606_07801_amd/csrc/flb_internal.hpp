@@ -84,6 +84,11 @@ struct flb_lattice {
   size_t res_lds;        // its LDS bytes
   int res_lds_max;       // the device's LDS bytes per workgroup
   char* prof_mem;        // density-profile buffers (library-allocated on first use)
+  // temperature and rates by region (flb_set_regions); reg_n = 0: uniform
+  int reg_n;
+  uint8_t* reg_map;      // region of every site (device, library-allocated)
+  char* reg_tab;         // kernel constants of every region (device)
+  double reg_theta[16], reg_omega[16][3];
 };
 
 namespace flb {

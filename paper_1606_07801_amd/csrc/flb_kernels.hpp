@@ -74,6 +74,35 @@ __global__ void __launch_bounds__(256) k_step_plain(const T* __restrict__ g, T* 
   for (int i = 0; i < Q; ++i) h[i * P.n + s] = f[i];
 }
 
+// Step of a lattice whose temperature and rates vary by region: site s
+// collides with the constants of region[s] (a table of at most 16 entries,
+// staged in LDS), streaming as in k_step_plain.
+constexpr int kMaxRegions = 16;
+
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_step_regions(const T* __restrict__ g, T* __restrict__ h,
+                                                      const KParams<T>* __restrict__ ptab, int nreg,
+                                                      const uint8_t* __restrict__ region, int64_t n,
+                                                      uint32_t step) {
+  constexpr int Q = 2 * D + 1;
+  __shared__ KParams<T> tab[kMaxRegions];
+  for (int r = threadIdx.x; r < nreg; r += blockDim.x) tab[r] = ptab[r];
+  __syncthreads();
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const KParams<T>& P = tab[region[s]];
+  const int64_t x = s % P.nx;
+  const int64_t rest = s / P.nx;
+  const int64_t y = rest % P.ny;
+  const int64_t z = rest / P.ny;
+  const Nbr b = neighbours(x, y, z, P.nx, P.ny, P.nz);
+  T f[Q];
+  gather<D, T>(g, n, b, f);
+  Collide<D, T>::run(f, P, (uint64_t)s, step);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) h[i * n + s] = f[i];
+}
+
 // Map a linear block index so that the blocks the dispatcher sends to one
 // XCD (round-robin over 8) cover one contiguous range of tiles, keeping the
 // shared halo lines of neighbouring tiles in one L2.

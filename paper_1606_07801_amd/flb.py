@@ -27,7 +27,8 @@ EXPORTS = (
     "flb_create", "flb_set_populations", "flb_get_populations", "flb_step",
     "flb_get_step", "flb_moments", "flb_structure_factor", "flb_set_sampling",
     "flb_set_moment_sampling", "flb_sampled_moments", "flb_set_correlation",
-    "flb_correlation", "flb_fourier_amplitudes", "flb_profile", "flb_sync", "flb_destroy",
+    "flb_correlation", "flb_fourier_amplitudes", "flb_profile", "flb_set_regions", "flb_sync",
+    "flb_destroy",
     "flb_noise_sample", "flb_batch_create", "flb_batch_admit", "flb_batch_retire",
     "flb_batch_step", "flb_batch_size", "flb_batch_sync", "flb_batch_destroy",
 )
@@ -110,6 +111,7 @@ def load(path=LIB_PATH):
         "flb_correlation": ([vp, dp, dp, ctypes.POINTER(i64)], ctypes.c_int),
         "flb_fourier_amplitudes": ([vp, dp], ctypes.c_int),
         "flb_profile": ([vp, i32, dp, dp], ctypes.c_int),
+        "flb_set_regions": ([vp, vp, i32, dp, dp], ctypes.c_int),
         "flb_sync": ([vp], ctypes.c_int),
         "flb_destroy": ([vp], ctypes.c_int),
         "flb_noise_sample": ([i32, i32, i32, u64, i64, i64, i64, vp, vp, vp], ctypes.c_int),
@@ -304,6 +306,21 @@ class Lattice:
         a = np.zeros((nk, self.Q, 2))
         check(load().flb_fourier_amplitudes(self.handle, a.ctypes.data))
         return a[..., 0] + 1j * a[..., 1]
+
+    def set_regions(self, region=None, theta=(), omega=()):
+        """Per-site region index (array of the lattice's shape, (.., y, x))
+        with theta[r] and omega[r] = omega_j or (omega_j, omega_n, omega_s)
+        per region; region=None returns to the uniform lattice."""
+        if region is None:
+            check(load().flb_set_regions(self.handle, None, 0, None, None))
+            return
+        reg = np.ascontiguousarray(region, dtype=np.uint8).reshape(-1)
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        om = np.zeros((len(th), 3))
+        for r, o in enumerate(omega):
+            o = np.atleast_1d(np.asarray(o, dtype=np.float64))
+            om[r, :len(o)] = o
+        check(load().flb_set_regions(self.handle, reg.ctypes.data, len(th), th.ctypes.data, om.ctypes.data))
 
     def profile(self, axis=0):
         """(sum of rho, sum of rho^2) over the sites of each coordinate along `axis`."""
