@@ -70,7 +70,12 @@ enum { FLB_LAYOUT_TWO_BUFFER = 0 };
  * workgroup (EINVAL at flb_create otherwise).  AUTO picks RESIDENT when it
  * fits, else ROWS. */
 enum { FLB_KERNEL_AUTO = 0, FLB_KERNEL_PLAIN = 1, FLB_KERNEL_ROWS = 2, FLB_KERNEL_FLAT = 3,
-       FLB_KERNEL_RESIDENT = 4 };
+       FLB_KERNEL_RESIDENT = 4, FLB_KERNEL_TWO_STEP = 5 };
+/* TWO_STEP (D2Q5 only; Q N precision < 2^32): pairs of steps between which
+ * nothing is sampled run as one pass over the lattice (tiles of 256 columns
+ * x tile_rows rows, 2..16, default 8, with a one-site halo recomputed by
+ * the neighbouring tiles), halving the populations' trips through HBM; the
+ * other steps take the flat kernel.  Bit-identical to single steps. */
 
 typedef struct flb_lattice flb_lattice; /* opaque */
 typedef struct flb_batch flb_batch;     /* opaque */
@@ -91,7 +96,8 @@ typedef struct {
   int32_t kernel;     /* FLB_KERNEL_* */
   int32_t tile_x;     /* rows kernel: threads per block along x (64..1024, multiple
                          of 64); 0 -> default */
-  int32_t tile_rows;  /* rows kernel: rows per thread (1, 2, 4, 8, 16); 0 -> default */
+  int32_t tile_rows;  /* rows kernel: rows per thread (1, 2, 4, 8, 16); flat: sites per lane
+                         in units of 256; two-step: rows per tile; 0 -> default */
   int32_t nt_store;   /* rows kernel: 1 = non-temporal stores of the new state */
   int32_t pipeline;   /* rows kernel: 1 = rows software-pipelined (next row's loads in
                          flight while the current row is collided), 0 = all rows of a

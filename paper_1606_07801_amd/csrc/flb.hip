@@ -77,8 +77,11 @@ int check_params(const flb_params* p) {
   if (p->noise < 0 || p->noise > 2) return fail(FLB_EINVAL, "noise must be 0 (local), 1 (global) or 2 (off)");
   if (p->noise_law < 0 || p->noise_law > 1) return fail(FLB_EINVAL, "noise_law must be 0 (Gauss) or 1 (uniform)");
   if (p->layout != FLB_LAYOUT_TWO_BUFFER) return fail(FLB_EINVAL, "layout must be FLB_LAYOUT_TWO_BUFFER");
-  if (p->kernel < 0 || p->kernel > 4)
-    return fail(FLB_EINVAL, "kernel must be 0 (auto), 1 (plain), 2 (rows), 3 (flat) or 4 (resident)");
+  if (p->kernel < 0 || p->kernel > 5)
+    return fail(FLB_EINVAL, "kernel must be 0 (auto), 1 (plain), 2 (rows), 3 (flat), 4 (resident) or 5 (two-step)");
+  if (p->kernel == FLB_KERNEL_TWO_STEP &&
+      (d != 2 || p->tile_rows > 16 || n * (2 * d + 1) * p->precision >= 4294967296.0))
+    return fail(FLB_EINVAL, "two-step kernel: D2Q5 only, tile_rows <= 16, Q * N * precision < 2^32");
   if (p->kernel == FLB_KERNEL_FLAT && (p->tile_rows > 8 || n * (2 * d + 1) * p->precision >= 4294967296.0))
     return fail(FLB_EINVAL, "flat kernel: tile_rows <= 8 and Q * N * precision < 2^32");
   if (p->tile_x != 0 && (p->tile_x < 64 || p->tile_x > 1024 || p->tile_x % 64 != 0))
@@ -182,12 +185,14 @@ int launch_step_t(flb_lattice* h, const T* g, T* out, uint32_t step, hipStream_t
     return 0;
   }
   const KParams<T> P = make_kparams<T>(h->p, h->rho_eq);
-  const int kern = h->p.kernel == FLB_KERNEL_AUTO ? FLB_KERNEL_ROWS : h->p.kernel;
+  // single steps of a two-step lattice take the flat kernel (2 rows per tile)
+  const int kern = h->p.kernel == FLB_KERNEL_AUTO ? FLB_KERNEL_ROWS
+                   : (h->p.kernel == FLB_KERNEL_TWO_STEP ? FLB_KERNEL_FLAT : h->p.kernel);
   if (kern == FLB_KERNEL_PLAIN) {
     const int64_t nb = (h->n + 255) / 256;
     k_step_plain<D, T><<<dim3((unsigned)nb), dim3(256), 0, st>>>(g, out, P, step);
   } else if (kern == FLB_KERNEL_FLAT) {
-    const int ry = h->p.tile_rows ? h->p.tile_rows : 2;
+    const int ry = h->p.kernel == FLB_KERNEL_TWO_STEP ? 2 : (h->p.tile_rows ? h->p.tile_rows : 2);
     const int64_t nb = (h->n + 256 * ry - 1) / (256 * ry);
     const bool nt = h->p.nt_store != 0;
 #define FLB_FLAT(RYV)                                                                     \
@@ -422,6 +427,41 @@ void launch_resident(flb_lattice* h, int c, size_t lds, int corr_lds) {
   h->corr_count += multiples_in(h->step, c, A.corr_every);
   h->cur = (h->cur + c) & 1;
   h->step += c;
+}
+
+// two D2Q5 steps in one pass (steps t and t + 1): g holds the state at t,
+// out receives the state at t + 2
+template <typename T>
+void launch_step2_t(flb_lattice* h, const T* g, T* out, uint32_t step) {
+  const KParams<T> P = make_kparams<T>(h->p, h->rho_eq);
+  const int ty = h->p.tile_rows ? h->p.tile_rows : 8;
+  const int tiles_x = (int)((h->p.n[0] + 255) / 256);
+  const bool nt = h->p.nt_store != 0;
+#define FLB_TWO(TYV)                                                                                    \
+  {                                                                                                     \
+    const unsigned nb = (unsigned)(tiles_x * ((h->p.n[1] + TYV - 1) / TYV));                             \
+    if (nt) k_step2_d2<T, TYV, true><<<nb, 256, 0, h->stream>>>(g, out, P, step, tiles_x);               \
+    else k_step2_d2<T, TYV, false><<<nb, 256, 0, h->stream>>>(g, out, P, step, tiles_x);                 \
+  }
+  switch (ty) {
+    case 1: case 2: FLB_TWO(2) break;
+    case 4: FLB_TWO(4) break;
+    case 16: FLB_TWO(16) break;
+    default: FLB_TWO(8) break;
+  }
+#undef FLB_TWO
+}
+
+void launch_step2(flb_lattice* h, const void* g, void* out, uint32_t step) {
+  if (h->s == 4) launch_step2_t<float>(h, (const float*)g, (float*)out, step);
+  else launch_step2_t<double>(h, (const double*)g, (double*)out, step);
+}
+
+// a statistic is sampled on the state before step t
+bool sample_due(const flb_lattice* h, int64_t t) {
+  return (h->mom_every > 0 && t % h->mom_every == 0) ||
+         (h->corr_mem && h->corr_every > 0 && t % h->corr_every == 0) ||
+         (h->sample_every > 0 && t % h->sample_every == 0);
 }
 
 // density profile along `axis` into out (sums of rho, then of rho^2)
@@ -869,6 +909,7 @@ int flb_step(flb_lattice* h, int64_t nsteps) {
     HIP_TRY(hipGetLastError());
     return FLB_OK;
   }
+  const bool two = h->p.kernel == FLB_KERNEL_TWO_STEP && h->reg_n == 0;
   for (int64_t k = 0; k < nsteps; ++k) {
     const int nxt = 1 - h->cur;
     const uint32_t t32 = (uint32_t)(h->step & 0xFFFFFFFF);
@@ -879,6 +920,14 @@ int flb_step(flb_lattice* h, int64_t nsteps) {
     }
     if (h->corr_every > 0 && h->step % h->corr_every == 0) corr_sample(h);  // state before this step
     const bool sample = h->sample_every > 0 && h->step % h->sample_every == 0;
+    if (two && !sample && k + 1 < nsteps && !sample_due(h, h->step + 1)) {
+      // steps t and t + 1 in one pass; nothing is sampled on the state between
+      launch_step2(h, lat_buffer(h, h->cur), lat_buffer(h, nxt), t32);
+      h->cur = nxt;
+      h->step += 2;
+      ++k;
+      continue;
+    }
     if (sample && h->sample_fused && h->reg_n == 0) {
       launch_step_sampled(h, lat_buffer(h, h->cur), lat_buffer(h, nxt), t32);
       launch_sk(h, 1, true);

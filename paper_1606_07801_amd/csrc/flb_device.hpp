@@ -20,6 +20,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// No implicit multiply-add contraction in the kernels: every kernel variant
+// (and every context a collision is inlined into) must round each site's
+// arithmetic identically, and which mul/add pairs the compiler fuses depends
+// on the surrounding code.  Fused operations are written out where wanted.
+#pragma clang fp contract(off)
+
 namespace flb {
 
 enum NoiseMode : int { kNoiseLocal = 0, kNoiseGlobal = 1, kNoiseOff = 2 };
@@ -167,7 +173,7 @@ struct Collide<1, T> {
     const double rho_d = density_sum(f);
     const T rho = (T)rho_d;
     const T Mj = P.a * (f[1] - f[2]);
-    const T Ms = P.c1 * (f[1] + f[2]) - P.c0 * f[0];
+    const T Ms = fma(P.c1, f[1] + f[2], -(P.c0 * f[0]));
     T xj = 0, xs = 0;
     if (P.noise != kNoiseOff) {
       T z[4];
@@ -176,10 +182,11 @@ struct Collide<1, T> {
       xj = sr * P.sq_j * z[0];
       xs = sr * P.sq_s * z[1];
     }
-    const T dj = xj - P.om_j * Mj;
-    const T ds = xs - P.om_s * Ms;
-    const T f1 = f[1] + P.w1 * (P.a * dj + P.c1 * ds);
-    const T f2 = f[2] + P.w1 * (P.c1 * ds - P.a * dj);
+    const T dj = fma(-P.om_j, Mj, xj);
+    const T ds = fma(-P.om_s, Ms, xs);
+    const T cj = P.a * dj, cs = P.c1 * ds;
+    const T f1 = fma(P.w1, cs + cj, f[1]);
+    const T f2 = fma(P.w1, cs - cj, f[2]);
     f[1] = f1;
     f[2] = f2;
     const T mv[2] = {f1, f2};
@@ -198,7 +205,7 @@ struct Collide<2, T> {
     const T Mx = P.a * (f[1] - f[2]);
     const T My = P.a * (f[3] - f[4]);
     const T Mn = P.b * (sx - sy);
-    const T Ms = P.c1 * (sx + sy) - P.c0 * f[0];
+    const T Ms = fma(P.c1, sx + sy, -(P.c0 * f[0]));
     T x1 = 0, x2 = 0, x3 = 0, x4 = 0;
     if (P.noise != kNoiseOff) {
       T z[4];
@@ -210,17 +217,17 @@ struct Collide<2, T> {
       x3 = sr * P.sq_n * z[2];
       x4 = sr * P.sq_s * z[3];
     }
-    const T dx = x1 - P.om_j * Mx;
-    const T dy = x2 - P.om_j * My;
-    const T dn = x3 - P.om_n * Mn;
-    const T ds = x4 - P.om_s * Ms;
+    const T dx = fma(-P.om_j, Mx, x1);
+    const T dy = fma(-P.om_j, My, x2);
+    const T dn = fma(-P.om_n, Mn, x3);
+    const T ds = fma(-P.om_s, Ms, x4);
     const T cx = P.a * dx, cy = P.a * dy;
     const T pn = P.b * dn, ps = P.c1 * ds;
     const T hx = pn + ps, hy = ps - pn;
-    const T f1 = f[1] + P.w1 * (hx + cx);
-    const T f2 = f[2] + P.w1 * (hx - cx);
-    const T f3 = f[3] + P.w1 * (hy + cy);
-    const T f4 = f[4] + P.w1 * (hy - cy);
+    const T f1 = fma(P.w1, hx + cx, f[1]);
+    const T f2 = fma(P.w1, hx - cx, f[2]);
+    const T f3 = fma(P.w1, hy + cy, f[3]);
+    const T f4 = fma(P.w1, hy - cy, f[4]);
     f[1] = f1;
     f[2] = f2;
     f[3] = f3;
@@ -243,7 +250,7 @@ struct Collide<3, T> {
     const T Mz = P.a * (f[5] - f[6]);
     const T Mn1 = P.b * (sx - sy);
     const T Mn2 = P.e * ((sx + sy) - (T)2 * sz);
-    const T Ms = P.c1 * ((sx + sy) + sz) - P.c0 * f[0];
+    const T Ms = fma(P.c1, (sx + sy) + sz, -(P.c0 * f[0]));
     T x[6] = {0, 0, 0, 0, 0, 0};
     if (P.noise != kNoiseOff) {
       T z[4], zz[4];
@@ -258,23 +265,23 @@ struct Collide<3, T> {
       x[4] = gn * zz[0];
       x[5] = sr * P.sq_s * zz[1];
     }
-    const T dx = x[0] - P.om_j * Mx;
-    const T dy = x[1] - P.om_j * My;
-    const T dz = x[2] - P.om_j * Mz;
-    const T dn1 = x[3] - P.om_n * Mn1;
-    const T dn2 = x[4] - P.om_n * Mn2;
-    const T ds = x[5] - P.om_s * Ms;
+    const T dx = fma(-P.om_j, Mx, x[0]);
+    const T dy = fma(-P.om_j, My, x[1]);
+    const T dz = fma(-P.om_j, Mz, x[2]);
+    const T dn1 = fma(-P.om_n, Mn1, x[3]);
+    const T dn2 = fma(-P.om_n, Mn2, x[4]);
+    const T ds = fma(-P.om_s, Ms, x[5]);
     const T cx = P.a * dx, cy = P.a * dy, cz = P.a * dz;
     const T p1 = P.b * dn1, p2 = P.e * dn2, ps = P.c1 * ds;
     const T hx = (p1 + p2) + ps;
     const T hy = (p2 - p1) + ps;
     const T hz = ps - (T)2 * p2;
-    const T f1 = f[1] + P.w1 * (hx + cx);
-    const T f2 = f[2] + P.w1 * (hx - cx);
-    const T f3 = f[3] + P.w1 * (hy + cy);
-    const T f4 = f[4] + P.w1 * (hy - cy);
-    const T f5 = f[5] + P.w1 * (hz + cz);
-    const T f6 = f[6] + P.w1 * (hz - cz);
+    const T f1 = fma(P.w1, hx + cx, f[1]);
+    const T f2 = fma(P.w1, hx - cx, f[2]);
+    const T f3 = fma(P.w1, hy + cy, f[3]);
+    const T f4 = fma(P.w1, hy - cy, f[4]);
+    const T f5 = fma(P.w1, hz + cz, f[5]);
+    const T f6 = fma(P.w1, hz - cz, f[6]);
     f[1] = f1;
     f[2] = f2;
     f[3] = f3;

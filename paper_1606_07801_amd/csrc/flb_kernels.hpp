@@ -219,25 +219,53 @@ __device__ __forceinline__ void flat_tile(const T* __restrict__ g, T* __restrict
   const uint32_t nx = (uint32_t)P.nx, ny = (uint32_t)P.ny, nz = (uint32_t)P.nz;
   const uint32_t n = (uint32_t)P.n;               // n * S < 2^32 (checked by the caller)
   const uint32_t nxy = nx * ny;
+  // coordinates of the tile's first site, uniform over the workgroup (scalar
+  // unit); when a row holds at least the tile's 256 RY sites a lane crosses
+  // at most one row end, so its coordinates follow by one compare instead of
+  // a per-lane division (quarter-rate integer multiplies)
+  const uint32_t s0u = (uint32_t)s0;
+  const uint32_t x0 = s0u % nx, r0 = s0u / nx;
+  const uint32_t y0 = D == 3 ? r0 % ny : r0, z0 = D == 3 ? r0 / ny : 0;
+  const bool wide = nx >= 256u * RY;
   T f[RY][Q];
   uint32_t sj[RY];
 #pragma unroll
   for (int j = 0; j < RY; ++j) {
-    const uint32_t s = (uint32_t)s0 + (uint32_t)j * 256u + lane;
+    const uint32_t off = (uint32_t)j * 256u + lane;
+    const uint32_t s = s0u + off;
     sj[j] = s;
     if (s < n) {
-      const uint32_t x = s % nx, rest = s / nx;
+      uint32_t x, rest, yw = 0, zw = 0;
+      if (wide) {
+        x = x0 + off;
+        const uint32_t c = x >= nx ? 1u : 0u;
+        x -= c ? nx : 0u;
+        rest = r0 + c;
+        if constexpr (D == 3) {
+          yw = y0 + c;
+          const uint32_t c2 = yw >= ny ? 1u : 0u;
+          yw -= c2 ? ny : 0u;
+          zw = z0 + c2;
+        }
+      } else {
+        x = s % nx;
+        rest = s / nx;
+        if constexpr (D == 3) {
+          yw = rest % ny;
+          zw = rest / ny;
+        }
+      }
       const uint32_t sxm = x == 0 ? s + nx - 1 : s - 1, sxp = x == nx - 1 ? s + 1 - nx : s + 1;
       f[j][0] = ld_at(g, s * S);
       f[j][1] = ld_at(g + n, sxm * S);
       f[j][2] = ld_at(g + 2 * (int64_t)n, sxp * S);
       if constexpr (D >= 2) {
-        const uint32_t y = D == 2 ? rest : rest % ny;
+        const uint32_t y = D == 2 ? rest : yw;
         const uint32_t sym = y == 0 ? s + nxy - nx : s - nx, syp = y == ny - 1 ? s + nx - nxy : s + nx;
         f[j][3] = ld_at(g + 3 * (int64_t)n, sym * S);
         f[j][4] = ld_at(g + 4 * (int64_t)n, syp * S);
         if constexpr (D >= 3) {
-          const uint32_t z = rest / ny;
+          const uint32_t z = zw;
           const uint32_t szm = z == 0 ? s + n - nxy : s - nxy, szp = z == nz - 1 ? s + nxy - n : s + nxy;
           f[j][5] = ld_at(g + 5 * (int64_t)n, szm * S);
           f[j][6] = ld_at(g + 6 * (int64_t)n, szp * S);
@@ -251,6 +279,95 @@ __device__ __forceinline__ void flat_tile(const T* __restrict__ g, T* __restrict
       Collide<D, T>::run(f[j], P, (uint64_t)sj[j], step);
 #pragma unroll
       for (int i = 0; i < Q; ++i) st_at<T, NT>(h + i * (int64_t)n, sj[j] * S, f[j][i]);
+    }
+  }
+}
+
+// Two D2Q5 steps per pass (temporal blocking).  A workgroup owns the
+// columns x0 .. x0 + w - 1 (w <= 256, one per lane) of the rows r0 .. r0 + hr - 1
+// (hr <= TY).  Step t: every lane collides its column for the rows r0 - 1 ..
+// r0 + hr (the owned rows plus one halo row on each side, periodic), and a
+// few lanes of wave 0 collide the halo columns x0 - 1 and x0 + w for the
+// owned rows.  Post-collision populations that move along x (f*_1 to the
+// right, f*_2 to the left) go through LDS; those moving along y stay in the
+// lane's registers.  Step t + 1: each owned site gathers
+//   f_0 = f*_0(x, r), f_1 = f*_1(x - 1, r), f_2 = f*_2(x + 1, r),
+//   f_3 = f*_3(x, r - 1), f_4 = f*_4(x, r + 1)
+// collides with the noise of step t + 1 and stores in the storage form.
+// Every collision is the per-site code of the one-step kernels on the same
+// inputs, so the result is bit-identical to two single steps; halo sites are
+// computed by more than one workgroup.  HBM traffic per two steps: reads
+// 5 (TY + 2) / TY and writes 5 per site, against 10 and 10.
+template <typename T, int TY, bool NT>
+__global__ void __launch_bounds__(256) k_step2_d2(const T* __restrict__ g, T* __restrict__ h,
+                                                  KParams<T> P, uint32_t step, int tiles_x) {
+  constexpr int Q = 5;
+  constexpr uint32_t S = sizeof(T);
+  __shared__ T l1[TY][258], l2[TY][258];  // [row][1 + lane]; 0: left halo (f*_1), 257: right halo (f*_2)
+  const uint32_t nx = (uint32_t)P.nx, ny = (uint32_t)P.ny, n = (uint32_t)P.n;
+  const int lane = threadIdx.x;
+  const uint32_t tx = blockIdx.x % (uint32_t)tiles_x, ty = blockIdx.x / (uint32_t)tiles_x;
+  const uint32_t x0 = tx * 256u, r0 = ty * (uint32_t)TY;
+  const int w = (int)(nx - x0 < 256u ? nx - x0 : 256u);
+  const int hr = (int)(ny - r0 < (uint32_t)TY ? ny - r0 : (uint32_t)TY);
+  // one collision of step t at (x, r) from the storage form g
+  auto first = [&](uint32_t x, uint32_t r, T (&f)[Q]) {
+    const uint32_t row = r * nx;
+    const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const uint32_t rm = (r == 0 ? ny - 1 : r - 1) * nx, rp = (r == ny - 1 ? 0 : r + 1) * nx;
+    f[0] = ld_at(g, (row + x) * S);
+    f[1] = ld_at(g + n, (row + xm) * S);
+    f[2] = ld_at(g + 2 * (int64_t)n, (row + xp) * S);
+    f[3] = ld_at(g + 3 * (int64_t)n, (rm + x) * S);
+    f[4] = ld_at(g + 4 * (int64_t)n, (rp + x) * S);
+    Collide<2, T>::run(f, P, (uint64_t)(row + x), step);
+  };
+  T fs[TY + 2][Q];
+  const bool own = lane < w;
+  if (own) {
+    const uint32_t x = x0 + (uint32_t)lane;
+#pragma unroll
+    for (int k = 0; k < TY + 2; ++k) {
+      if (k <= hr + 1) {
+        const int rr = (int)r0 - 1 + k;  // -1 .. r0 + hr
+        const uint32_t r = rr < 0 ? (uint32_t)(rr + (int)ny) : ((uint32_t)rr >= ny ? (uint32_t)rr - ny : (uint32_t)rr);
+        first(x, r, fs[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < TY; ++k) {
+      if (k < hr) {
+        l1[k][1 + lane] = fs[k + 1][1];
+        l2[k][1 + lane] = fs[k + 1][2];
+      }
+    }
+  }
+  if (lane < 2 * TY) {  // halo columns: lanes 0 .. TY-1 left (f*_1), TY .. 2TY-1 right (f*_2)
+    const int k = lane < TY ? lane : lane - TY;
+    if (k < hr) {
+      const uint32_t xh = lane < TY ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + (uint32_t)w == nx ? 0 : x0 + (uint32_t)w);
+      T fh[Q];
+      first(xh, r0 + (uint32_t)k, fh);
+      if (lane < TY) l1[k][0] = fh[1];
+      else l2[k][1 + w] = fh[2];
+    }
+  }
+  __syncthreads();
+  if (!own) return;
+  const uint32_t x = x0 + (uint32_t)lane;
+#pragma unroll
+  for (int k = 0; k < TY; ++k) {
+    if (k < hr) {
+      T f[Q];
+      f[0] = fs[k + 1][0];
+      f[1] = l1[k][lane];
+      f[2] = l2[k][lane + 2];
+      f[3] = fs[k][3];
+      f[4] = fs[k + 2][4];
+      const uint32_t s = (r0 + (uint32_t)k) * nx + x;
+      Collide<2, T>::run(f, P, (uint64_t)s, step + 1u);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) st_at<T, NT>(h + i * (int64_t)n, s * S, f[i]);
     }
   }
 }

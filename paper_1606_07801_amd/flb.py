@@ -18,7 +18,7 @@ FLB_OK, FLB_EINVAL, FLB_ENOMEM, FLB_EDEVICE, FLB_ESTATE, FLB_ENONFINITE = 0, -1,
 MODELS = {"D1Q3": 1, "D2Q5": 2, "D3Q7": 3, 1: 1, 2: 2, 3: 3}
 NOISE = {"local": 0, "global": 1, "off": 2}
 LAWS = {"gauss": 0, "uniform": 1}
-KERNELS = {"auto": 0, "plain": 1, "rows": 2, "flat": 3, "resident": 4}
+KERNELS = {"auto": 0, "plain": 1, "rows": 2, "flat": 3, "resident": 4, "two": 5}
 SK_SNAPSHOT, SK_SAMPLE, SK_READ, SK_RESET = 0, 1, 2, 3
 
 # exported symbols, in the order include/flb.h declares them
