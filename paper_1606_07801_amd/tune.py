@@ -23,11 +23,12 @@ DEFAULTS = {1: dict(kernel="rows", tile_x=256, tile_rows=1, nt_store=0),
             3: dict(kernel="rows", tile_x=256, tile_rows=4, nt_store=0)}
 
 CANDIDATES = ([("plain", 0, 0, 0, 0), ("resident", 0, 0, 0, 0)] +
+              [("two", 0, ty, nt, 0) for ty in (4, 8, 16) for nt in (0, 1)] +
               [("flat", 0, ry, nt, 0) for ry in (1, 2, 4, 8) for nt in (0, 1)] +
               [("rows", tx, ry, nt, 0) for tx in (64, 128, 256, 512, 1024) for ry in (1, 2, 4, 8, 16)
                for nt in (0, 1)] +
               [("rows", tx, ry, nt, 1) for tx in (128, 256, 512) for ry in (2, 4, 8, 16) for nt in (0, 1)])
-QUICK = ([("plain", 0, 0, 0, 0), ("resident", 0, 0, 0, 0)] +
+QUICK = ([("plain", 0, 0, 0, 0), ("resident", 0, 0, 0, 0), ("two", 0, 8, 1, 0), ("two", 0, 16, 1, 0)] +
          [("flat", 0, ry, nt, 0) for ry in (1, 2, 4) for nt in (0, 1)] +
          [("rows", tx, ry, 1, 0) for tx in (256, 512) for ry in (1, 2, 4)])
 
