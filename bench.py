@@ -29,25 +29,34 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step_d2q5_4096_fp32_traffic.md
 
 
 def measured_traffic(kernel):
-    """HBM bytes per step launch from the committed counter summary, or None
-    if the step kernel's sources or its launch configuration changed since the
-    counters were taken."""
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None if the step kernels' sources changed since the counters were
+    taken or the summary has no entry for that kernel.  The summary lists
+    blocks of "kernel: <name>" followed by "traffic_bytes_per_launch: <n>"."""
     import hashlib
     try:
-        vals = {}
+        entries, cur, src = {}, None, None
         for line in open(TRAFFIC_PROFILE):
-            if ":" in line and not line.startswith(("#", "|", " ", "`")):
-                k, v = line.split(":", 1)
-                vals[k.strip()] = v.strip()
+            if ":" not in line or line.startswith(("#", "|", " ", "`")):
+                continue
+            k, v = (x.strip() for x in line.split(":", 1))
+            if k == "kernel_source_sha256_16":
+                src = v
+            elif k == "kernel":
+                cur = v
+            elif k == "traffic_bytes_per_launch" and cur:
+                entries[cur] = int(float(v))
         h = hashlib.sha256()
         for f in ("flb_device.hpp", "flb_kernels.hpp"):
             with open(os.path.join(ROOT, "paper_1606_07801_amd", "csrc", f), "rb") as fh:
                 h.update(fh.read())
-        if h.hexdigest()[:16] != vals.get("kernel_source_sha256_16") or vals.get("kernel") != kernel:
+        if h.hexdigest()[:16] != src:
             return None
-        return int(float(vals["traffic_bytes_per_launch"]))
-    except (OSError, KeyError, ValueError):
+        return entries.get(kernel)
+    except (OSError, ValueError):
         return None
+
+
 
 
 def parse():
@@ -128,6 +137,29 @@ def time_steps(torch, L, steps, sample_every, per_launch=1):
     return (t1 - t0) * 1e3 / steps, total / launches
 
 
+def depth1_reference(torch, flb, f0, dims):
+    """The one-step flat kernel on the same lattice (each step reads and
+    writes every population once): its duration and HBM roofline fraction,
+    the reference for the two-step pass."""
+    cfg = {"kernel": "flat", "tile_rows": 2, "nt_store": 1}
+    L = flb.Lattice(2, dims, precision=4, omega=1.0, seed=0, noise="local", **cfg)
+    L.set_populations(f0)
+    L.step(20)
+    st = L.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    L.step(100)
+    e1.record(st)
+    e1.synchronize()
+    L.close()
+    us = e0.elapsed_time(e1) * 1e3 / 100
+    name = kernel_name(cfg)
+    nbytes = 2 * 5 * 4 * dims[0] * dims[1]
+    gbs = nbytes / (us * 1e-6) / 1e9
+    return {"kernel": name, "kernel_us": round(us, 2), "achieved": round(gbs, 1),
+            "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": measured_traffic(name)}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -162,6 +194,7 @@ def main():
     m = L.moments()
     S = L.structure_factor(None, mode="read")[:len(kvecs)] if args.sample_every else np.zeros(1)
     L.close()
+    depth1 = depth1_reference(torch, flb, f0, dims)
 
     value = N / (ms_step * 1e-3) / 1e6  # MLUPS of the whole job
     # algorithmic: every step reads and writes every population once; a
@@ -189,6 +222,7 @@ def main():
             "measured_hbm_gbs": round(traffic / (kern_ms * 1e-3) / 1e9, 1) if traffic else None,
         },
         "step_kernel_mlups": round(spl * N / (kern_ms * 1e-3) / 1e6, 1),
+        "depth1": depth1,
         "mass_drift_rel": abs(m["mass"] - m["mass0"]) / m["mass0"],
         "sk_median_over_rho": float(np.median(S) / m["rho_eq"]),
     }
