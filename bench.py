@@ -115,8 +115,10 @@ def time_steps(torch, L, steps, sample_every, per_launch=1):
     t0 = time.perf_counter()
     while t < end:
         if sample_every and t % sample_every == 0:
-            L.step(1)                      # the sampled step (its own fused kernel)
-            t += 1
+            # the sampled step: alone, or the first of a sampled pair
+            k = 2 if per_launch == 2 and t + 1 < end and (t + 1) % sample_every else 1
+            L.step(k)
+            t += k
             continue
         nxt = min(end, (t // sample_every + 1) * sample_every) if sample_every else end
         run = nxt - t

@@ -452,9 +452,29 @@ void launch_step2_t(flb_lattice* h, const T* g, T* out, uint32_t step) {
 #undef FLB_TWO
 }
 
+// the same pass writing the density partials of the state at t (tiles of
+// kSampleRows rows, as the sampled one-step kernel)
+template <typename T>
+void launch_step2_sampled_t(flb_lattice* h, const T* g, T* out, uint32_t step) {
+  const KParams<T> P = make_kparams<T>(h->p, h->rho_eq);
+  const int tiles_x = (int)((h->p.n[0] + 255) / 256);
+  const unsigned nb = (unsigned)(tiles_x * ((h->p.n[1] + kSampleRows - 1) / kSampleRows));
+  double* rp = (double*)(h->work + h->wl.rowpart);
+  double* cp = (double*)(h->work + h->wl.colbig);
+  if (h->p.nt_store)
+    k_step2_d2<T, kSampleRows, true, true><<<nb, 256, 0, h->stream>>>(g, out, P, step, tiles_x, rp, cp);
+  else
+    k_step2_d2<T, kSampleRows, false, true><<<nb, 256, 0, h->stream>>>(g, out, P, step, tiles_x, rp, cp);
+}
+
 void launch_step2(flb_lattice* h, const void* g, void* out, uint32_t step) {
   if (h->s == 4) launch_step2_t<float>(h, (const float*)g, (float*)out, step);
   else launch_step2_t<double>(h, (const double*)g, (double*)out, step);
+}
+
+void launch_step2_sampled(flb_lattice* h, const void* g, void* out, uint32_t step) {
+  if (h->s == 4) launch_step2_sampled_t<float>(h, (const float*)g, (float*)out, step);
+  else launch_step2_sampled_t<double>(h, (const double*)g, (double*)out, step);
 }
 
 // a statistic is sampled on the state before step t
@@ -910,6 +930,7 @@ int flb_step(flb_lattice* h, int64_t nsteps) {
     return FLB_OK;
   }
   const bool two = h->p.kernel == FLB_KERNEL_TWO_STEP && h->reg_n == 0;
+  const bool two_sk = two && (h->p.tile_rows ? h->p.tile_rows : 8) == kSampleRows;
   for (int64_t k = 0; k < nsteps; ++k) {
     const int nxt = 1 - h->cur;
     const uint32_t t32 = (uint32_t)(h->step & 0xFFFFFFFF);
@@ -920,6 +941,16 @@ int flb_step(flb_lattice* h, int64_t nsteps) {
     }
     if (h->corr_every > 0 && h->step % h->corr_every == 0) corr_sample(h);  // state before this step
     const bool sample = h->sample_every > 0 && h->step % h->sample_every == 0;
+    if (two_sk && sample && h->sample_fused && k + 1 < nsteps && !sample_due(h, h->step + 1)) {
+      // a sampled pair: the pass also writes the density partials of the state at t
+      launch_step2_sampled(h, lat_buffer(h, h->cur), lat_buffer(h, nxt), t32);
+      launch_sk(h, 1, true);
+      sk_accumulate(h);
+      h->cur = nxt;
+      h->step += 2;
+      ++k;
+      continue;
+    }
     if (two && !sample && k + 1 < nsteps && !sample_due(h, h->step + 1)) {
       // steps t and t + 1 in one pass; nothing is sampled on the state between
       launch_step2(h, lat_buffer(h, h->cur), lat_buffer(h, nxt), t32);

@@ -19,7 +19,7 @@ constexpr int kCorrBlocks = 256;   // site blocks of the Fourier-sum pass
 constexpr int kSkChunks = 256;    // site chunks of the direct structure factor
 constexpr int kColChunks = 64;    // row chunks of the column marginals
 constexpr int kNVals = 40;        // lattice sums (see k_moments_partial)
-constexpr int kSampleRows = 16;   // rows per tile of the sampled step
+constexpr int kSampleRows = 8;    // rows per tile of the sampled step (and of a sampled two-step pass)
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 

@@ -298,20 +298,31 @@ __device__ __forceinline__ void flat_tile(const T* __restrict__ g, T* __restrict
 // inputs, so the result is bit-identical to two single steps; halo sites are
 // computed by more than one workgroup.  HBM traffic per two steps: reads
 // 5 (TY + 2) / TY and writes 5 per site, against 10 and 10.
-template <typename T, int TY, bool NT>
+// SAMPLE: the pass also writes the FP64 density partials of the state at t
+// (the input of the axis structure factor), with the layout and the
+// reduction order of k_step_rows_sk for tiles of TY rows:
+//   rowpart[tx * nrows + row] = sum over the tile's columns of rho(x, row)
+//   colpart[ty * nx + x]      = sum over the tile's rows of rho(x, row)
+template <typename T, int TY, bool NT, bool SAMPLE = false>
 __global__ void __launch_bounds__(256) k_step2_d2(const T* __restrict__ g, T* __restrict__ h,
-                                                  KParams<T> P, uint32_t step, int tiles_x) {
+                                                  KParams<T> P, uint32_t step, int tiles_x,
+                                                  double* __restrict__ rowpart = nullptr,
+                                                  double* __restrict__ colpart = nullptr) {
   constexpr int Q = 5;
   constexpr uint32_t S = sizeof(T);
+  constexpr int NP = 256 / TY;
   __shared__ T l1[TY][258], l2[TY][258];  // [row][1 + lane]; 0: left halo (f*_1), 257: right halo (f*_2)
+  __shared__ double red[SAMPLE ? TY : 1][SAMPLE ? 256 : 1];
+  __shared__ double red2[SAMPLE ? TY : 1][SAMPLE ? NP : 1];
   const uint32_t nx = (uint32_t)P.nx, ny = (uint32_t)P.ny, n = (uint32_t)P.n;
   const int lane = threadIdx.x;
   const uint32_t tx = blockIdx.x % (uint32_t)tiles_x, ty = blockIdx.x / (uint32_t)tiles_x;
   const uint32_t x0 = tx * 256u, r0 = ty * (uint32_t)TY;
   const int w = (int)(nx - x0 < 256u ? nx - x0 : 256u);
   const int hr = (int)(ny - r0 < (uint32_t)TY ? ny - r0 : (uint32_t)TY);
-  // one collision of step t at (x, r) from the storage form g
-  auto first = [&](uint32_t x, uint32_t r, T (&f)[Q]) {
+  // one collision of step t at (x, r) from the storage form g; *rho receives
+  // the pre-collision density when asked for
+  auto first = [&](uint32_t x, uint32_t r, T (&f)[Q], double* rho) {
     const uint32_t row = r * nx;
     const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
     const uint32_t rm = (r == 0 ? ny - 1 : r - 1) * nx, rp = (r == ny - 1 ? 0 : r + 1) * nx;
@@ -320,6 +331,7 @@ __global__ void __launch_bounds__(256) k_step2_d2(const T* __restrict__ g, T* __
     f[2] = ld_at(g + 2 * (int64_t)n, (row + xp) * S);
     f[3] = ld_at(g + 3 * (int64_t)n, (rm + x) * S);
     f[4] = ld_at(g + 4 * (int64_t)n, (rp + x) * S);
+    if (rho) *rho = density_sum(f);
     Collide<2, T>::run(f, P, (uint64_t)(row + x), step);
   };
   T fs[TY + 2][Q];
@@ -331,8 +343,21 @@ __global__ void __launch_bounds__(256) k_step2_d2(const T* __restrict__ g, T* __
       if (k <= hr + 1) {
         const int rr = (int)r0 - 1 + k;  // -1 .. r0 + hr
         const uint32_t r = rr < 0 ? (uint32_t)(rr + (int)ny) : ((uint32_t)rr >= ny ? (uint32_t)rr - ny : (uint32_t)rr);
-        first(x, r, fs[k]);
+        if constexpr (SAMPLE) {
+          double rho = 0;
+          first(x, r, fs[k], (k >= 1 && k <= hr) ? &rho : nullptr);
+          if (k >= 1 && k <= TY) red[k - 1][lane] = (k <= hr) ? rho : 0.0;
+        } else {
+          first(x, r, fs[k], nullptr);
+        }
+      } else if constexpr (SAMPLE) {
+        if (k >= 1 && k <= TY) red[k - 1][lane] = 0.0;
       }
+    }
+    if constexpr (SAMPLE) {
+      double col = 0;
+      for (int k = 0; k < hr; ++k) col += red[k][lane];
+      colpart[(int64_t)ty * nx + x] = col;
     }
 #pragma unroll
     for (int k = 0; k < TY; ++k) {
@@ -347,12 +372,29 @@ __global__ void __launch_bounds__(256) k_step2_d2(const T* __restrict__ g, T* __
     if (k < hr) {
       const uint32_t xh = lane < TY ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + (uint32_t)w == nx ? 0 : x0 + (uint32_t)w);
       T fh[Q];
-      first(xh, r0 + (uint32_t)k, fh);
+      first(xh, r0 + (uint32_t)k, fh, nullptr);
       if (lane < TY) l1[k][0] = fh[1];
       else l2[k][1 + w] = fh[2];
     }
   }
+  if constexpr (SAMPLE) {
+    if (!own)
+      for (int k = 0; k < TY; ++k) red[k][lane] = 0.0;
+  }
   __syncthreads();
+  if constexpr (SAMPLE) {  // row partials: TY consecutive columns, then the NP partials in order
+    const int rr = lane / NP, part = lane % NP;
+    double acc = 0;
+#pragma unroll
+    for (int j = 0; j < TY; ++j) acc += red[rr][part * TY + j];
+    red2[rr][part] = acc;
+    __syncthreads();
+    if (lane < TY && lane < hr) {
+      double a2 = 0;
+      for (int p2 = 0; p2 < NP; ++p2) a2 += red2[lane][p2];
+      rowpart[(int64_t)tx * ny + r0 + lane] = a2;
+    }
+  }
   if (!own) return;
   const uint32_t x = x0 + (uint32_t)lane;
 #pragma unroll

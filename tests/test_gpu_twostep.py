@@ -68,3 +68,23 @@ def test_two_step_matches_oracle():
     fo = oracle.run(f0, oracle.Params(d=2, omega_j=1.3, omega_n=0.8, seed=99), 10)
     w = oracle.make_lattice(2).w
     assert report("two-step D2 (300, 70) fp64", scaled_error(g, fo, 10.0, w)) <= RTOL[8]
+
+
+@pytest.mark.parametrize("precision", [4, 8])
+def test_sampled_pairs_equal_single_steps(precision):
+    # axis-only k-list: the sampled step is fused into a pair whose pass also
+    # writes the density partials; state and S(k) sums equal the one-step path
+    dims = (300, 70)
+    ks = [[1, 0], [0, 1], [5, 0], [0, 7], [0, 0]]
+    out = []
+    for kern, ty in (("flat", 2), ("two", 8)):
+        dt = np.float32 if precision == 4 else np.float64
+        f0 = poisson_state(2, dims, 10.0, seed=4).astype(dt)
+        L = gpu_lattice(2, dims, precision, seed=3, kernel=kern, tile_rows=ty, nt_store=1)
+        L.set_populations(f0)
+        L.set_sampling(4, ks)
+        L.step(23)
+        out.append((L.get_populations(), L.structure_factor(mode="read")[:len(ks)]))
+        L.close()
+    assert np.array_equal(out[0][0].view(np.uint8), out[1][0].view(np.uint8))
+    assert np.array_equal(out[0][1], out[1][1])
