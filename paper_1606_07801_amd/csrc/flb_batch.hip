@@ -29,8 +29,15 @@ struct BatchRep {
   int64_t nrows;    // ny * nz
   int64_t step0;    // steps completed at the start of the chunk
   int32_t cur0;     // buffer holding the state at the start of the chunk
-  int32_t pad;
+  int32_t depth;    // 2: D2Q5 member stepped in two-step passes (one buffer swap per pass)
 };
+
+// Buffer holding a member's state k steps into a chunk: one swap per step,
+// or per two-step pass (a trailing single step of an odd chunk swaps once).
+template <typename T>
+__device__ __forceinline__ int member_parity(const BatchRep<T>& R, int k) {
+  return R.depth == 2 ? (R.cur0 + (k + 1) / 2) & 1 : (R.cur0 + k) & 1;
+}
 
 // A work item is a tile of kBatchTX columns x `rows` rows (a multiple of
 // kBatchRY), run by one kBatchTX-thread workgroup in sub-tiles of kBatchRY
@@ -53,10 +60,33 @@ __global__ void __launch_bounds__(256) k_batch_flat(const BatchRep<T>* __restric
     const BatchRep<T>& R = reps[r];
     const KParams<T> P = R.P;
     const uint32_t step = (uint32_t)((uint64_t)(R.step0 + k) & 0xFFFFFFFFull);
-    const int par = (R.cur0 + k) & 1;
+    const int par = member_parity(R, k);
     const T* g = (const T*)(R.pop + par * R.plane);
     T* h = (T*)(R.pop + (par ^ 1) * R.plane);
     flat_tile<D, T, kBatchRY, true>(g, h, P, step, tile * 256 * kBatchRY, threadIdx.x);
+  }
+}
+
+// Two-step work list (D2Q5 members at depth 2): item w is the tile
+// item_tile[w] = ty * tiles_x + tx (256 columns x kBatchTwoTY rows) of member
+// item_rep[w]; steps k and k + 1 of the chunk in one pass.
+constexpr int kBatchTwoTY = 8;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_batch_two(const BatchRep<T>* __restrict__ reps,
+                                                   const int32_t* __restrict__ item_rep,
+                                                   const int32_t* __restrict__ item_tile, int nitems, int k) {
+  for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+    const int r = __builtin_amdgcn_readfirstlane(item_rep[w]);
+    const uint32_t tile = __builtin_amdgcn_readfirstlane(item_tile[w]);
+    const BatchRep<T>& R = reps[r];
+    const KParams<T> P = R.P;
+    const uint32_t step = (uint32_t)((uint64_t)(R.step0 + k) & 0xFFFFFFFFull);
+    const int par = member_parity(R, k);
+    const T* g = (const T*)(R.pop + par * R.plane);
+    T* h = (T*)(R.pop + (par ^ 1) * R.plane);
+    const uint32_t tx2 = (uint32_t)((P.nx + 255) / 256);
+    step2_tile<T, kBatchTwoTY, true, false>(g, h, P, step, tile % tx2, tile / tx2, nullptr, nullptr);
   }
 }
 
@@ -71,7 +101,7 @@ __global__ void __launch_bounds__(kBatchTX) k_batch_rows(const BatchRep<T>* __re
     const BatchRep<T>& R = reps[r];
     const KParams<T> P = R.P;
     const uint32_t step = (uint32_t)((uint64_t)(R.step0 + k) & 0xFFFFFFFFull);
-    const int par = (R.cur0 + k) & 1;
+    const int par = member_parity(R, k);
     const T* g = (const T*)(R.pop + par * R.plane);
     T* h = (T*)(R.pop + (par ^ 1) * R.plane);
     const int64_t tx = tile % R.tiles_x, tr = tile / R.tiles_x;
@@ -151,8 +181,8 @@ template <typename T>
 __global__ void k_batch_advance(BatchRep<T>* __restrict__ reps, int n, int c) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
+    reps[i].cur0 = member_parity(reps[i], c);
     reps[i].step0 += c;
-    reps[i].cur0 = (reps[i].cur0 + c) & 1;
   }
 }
 
@@ -170,8 +200,10 @@ struct flb_batch {
   // device table: reps, then the item lists and the LDS member list
   char* d_table;
   size_t table_cap;
-  size_t off_items[7][2];  // per class (d = 1..3 row tiles, d + 3 flat tiles): item_rep, item_tile
-  int nitems[7];
+  // per class: d = 1..3 row tiles, d + 3 flat tiles, 7 two-step tiles and 8
+  // flat tiles of the depth-2 members (their odd trailing step); item_rep, item_tile
+  size_t off_items[9][2];
+  int nitems[9];
   size_t off_lds;
   int nlds, lds_spt;
   size_t lds_bytes;
@@ -216,7 +248,7 @@ template <typename T>
 int rebuild_t(flb_batch* b) {
   const int n = (int)b->members.size();
   std::vector<BatchRep<T>> reps(n);
-  std::vector<int32_t> items[7][2];
+  std::vector<int32_t> items[9][2];
   std::vector<int32_t> lds;
   int64_t lmax = 0;
   const int64_t lds_max = b->o.lds_max_bytes < 0 ? -1 : (b->o.lds_max_bytes ? b->o.lds_max_bytes : 65536);
@@ -239,6 +271,23 @@ int rebuild_t(flb_batch* b) {
     }
     const int64_t item_rows = (int64_t)kBatchRY * b->sub;
     const bool flat = b->o.tiling == 0 && (int64_t)h->plane < (1ll << 32);
+    if (b->o.depth == 2 && h->d == 2 && (int64_t)h->plane < (1ll << 32)) {
+      R.depth = 2;
+      const int64_t t2 = ((h->p.n[0] + 255) / 256) * ((h->p.n[1] + kBatchTwoTY - 1) / kBatchTwoTY);
+      const int64_t tf = (h->n + 256 * kBatchRY - 1) / (256 * kBatchRY);
+      if (t2 >= (1ll << 31) || tf >= (1ll << 31)) return fail(FLB_EINVAL, "member %d has too many tiles", i);
+      for (int64_t t = 0; t < t2; ++t) {
+        items[7][0].push_back(i);
+        items[7][1].push_back((int32_t)t);
+      }
+      R.tiles_x = -1;
+      for (int64_t t = 0; t < tf; ++t) {
+        items[8][0].push_back(i);
+        items[8][1].push_back((int32_t)t);
+      }
+      continue;
+    }
+    R.depth = 1;
     if (flat) R.tiles_x = -1;  // marks a flat member
     const int64_t ntile = flat ? (h->n + 256 * kBatchRY - 1) / (256 * kBatchRY)
                                : R.tiles_x * ((R.nrows + item_rows - 1) / item_rows);
@@ -250,7 +299,7 @@ int rebuild_t(flb_batch* b) {
     }
   }
   size_t o = align256(sizeof(BatchRep<T>) * std::max(n, 1));
-  for (int d = 1; d <= 6; ++d) {
+  for (int d = 1; d <= 8; ++d) {
     b->nitems[d] = (int)items[d][0].size();
     b->off_items[d][0] = o;
     o += align256(sizeof(int32_t) * std::max<size_t>(items[d][0].size(), 1));
@@ -267,7 +316,7 @@ int rebuild_t(flb_batch* b) {
     b->table_cap = o;
   }
   HIP_TRY(hipMemcpy(b->d_table, reps.data(), sizeof(BatchRep<T>) * n, hipMemcpyHostToDevice));
-  for (int d = 1; d <= 6; ++d)
+  for (int d = 1; d <= 8; ++d)
     for (int k = 0; k < 2; ++k)
       if (!items[d][k].empty())
         HIP_TRY(hipMemcpy(b->d_table + b->off_items[d][k], items[d][k].data(),
@@ -296,6 +345,23 @@ void enqueue_chunk_t(flb_batch* b, int c) {
       case 4: k_batch_lds_d1<T, 4><<<grid, block, b->lds_bytes, st>>>(reps, lr, c); break;
       case 8: k_batch_lds_d1<T, 8><<<grid, block, b->lds_bytes, st>>>(reps, lr, c); break;
       default: k_batch_lds_d1<T, 16><<<grid, block, b->lds_bytes, st>>>(reps, lr, c); break;
+    }
+  }
+  if (b->nitems[7] > 0) {  // depth-2 members: two-step passes, a single flat step for an odd chunk
+    const int32_t* ir2 = (const int32_t*)(b->d_table + b->off_items[7][0]);
+    const int32_t* it2 = (const int32_t*)(b->d_table + b->off_items[7][1]);
+    const int32_t* ir1 = (const int32_t*)(b->d_table + b->off_items[8][0]);
+    const int32_t* it1 = (const int32_t*)(b->d_table + b->off_items[8][1]);
+    for (int k = 0; k < c; k += 2) {
+      if (k + 1 < c) {
+        const int ni = b->nitems[7];
+        const int grid = b->o.workers > 0 ? std::max(1, std::min(ni, b->o.workers)) : ni;
+        k_batch_two<T><<<grid, 256, 0, st>>>(reps, ir2, it2, ni, k);
+      } else {
+        const int ni = b->nitems[8];
+        const int grid = b->o.workers > 0 ? std::max(1, std::min(ni, b->o.workers)) : ni;
+        k_batch_flat<2, T><<<grid, 256, 0, st>>>(reps, ir1, it1, ni, k);
+      }
     }
   }
   for (int k = 0; k < c; ++k) {
@@ -372,6 +438,8 @@ int flb_batch_create(const flb_batch_opts* opts, flb_batch** out) {
   if (o.tiling < 0 || o.tiling > 1) return fail(FLB_EINVAL, "tiling must be 0 (flat) or 1 (rows)");
   if (o.item_rows != 0 && o.item_rows != 2 && o.item_rows != 4 && o.item_rows != 8 && o.item_rows != 16)
     return fail(FLB_EINVAL, "item_rows must be 2, 4, 8 or 16");
+  if (o.depth < 0 || o.depth > 2) return fail(FLB_EINVAL, "depth must be 0 (default), 1 or 2");
+  if (o.depth == 0) o.depth = 2;
   if (o.chunk == 0) o.chunk = 16;
   flb_batch* b = new (std::nothrow) flb_batch();
   if (!b) return fail(FLB_ENOMEM, "batch allocation failed");
@@ -385,7 +453,7 @@ int flb_batch_create(const flb_batch_opts* opts, flb_batch** out) {
   b->nlds = 0;
   b->nreps = 0;
   b->sub = o.item_rows ? o.item_rows / kBatchRY : 1;
-  for (int d = 0; d < 7; ++d) b->nitems[d] = 0;
+  for (int d = 0; d < 9; ++d) b->nitems[d] = 0;
   hipError_t e = hipGetDevice(&b->device);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, b->device);
   if (e != hipSuccess) {
@@ -464,9 +532,12 @@ int flb_batch_step(flb_batch* b, int64_t nsteps) {
   }
   if (rem) enqueue_chunk(b, rem);
   HIP_TRY(hipGetLastError());
+  // buffer swaps of each member, chunk by chunk (depth-2 D2Q5 members swap once per pass)
   for (flb_lattice* h : b->members) {
+    const bool two = b->o.depth == 2 && h->d == 2 && (int64_t)h->plane < (1ll << 32);
+    const int64_t swaps = two ? chunks * ((c + 1) / 2) + (rem + 1) / 2 : nsteps;
     h->step += nsteps;
-    h->cur = (int)((h->cur + nsteps) & 1);
+    h->cur = (int)((h->cur + swaps) & 1);
   }
   return FLB_OK;
 }

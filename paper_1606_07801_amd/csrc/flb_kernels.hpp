@@ -303,11 +303,10 @@ __device__ __forceinline__ void flat_tile(const T* __restrict__ g, T* __restrict
 // reduction order of k_step_rows_sk for tiles of TY rows:
 //   rowpart[tx * nrows + row] = sum over the tile's columns of rho(x, row)
 //   colpart[ty * nx + x]      = sum over the tile's rows of rho(x, row)
-template <typename T, int TY, bool NT, bool SAMPLE = false>
-__global__ void __launch_bounds__(256) k_step2_d2(const T* __restrict__ g, T* __restrict__ h,
-                                                  KParams<T> P, uint32_t step, int tiles_x,
-                                                  double* __restrict__ rowpart = nullptr,
-                                                  double* __restrict__ colpart = nullptr) {
+template <typename T, int TY, bool NT, bool SAMPLE>
+__device__ __forceinline__ void step2_tile(const T* __restrict__ g, T* __restrict__ h, const KParams<T>& P,
+                                           uint32_t step, uint32_t tx, uint32_t ty,
+                                           double* __restrict__ rowpart, double* __restrict__ colpart) {
   constexpr int Q = 5;
   constexpr uint32_t S = sizeof(T);
   constexpr int NP = 256 / TY;
@@ -316,7 +315,6 @@ __global__ void __launch_bounds__(256) k_step2_d2(const T* __restrict__ g, T* __
   __shared__ double red2[SAMPLE ? TY : 1][SAMPLE ? NP : 1];
   const uint32_t nx = (uint32_t)P.nx, ny = (uint32_t)P.ny, n = (uint32_t)P.n;
   const int lane = threadIdx.x;
-  const uint32_t tx = blockIdx.x % (uint32_t)tiles_x, ty = blockIdx.x / (uint32_t)tiles_x;
   const uint32_t x0 = tx * 256u, r0 = ty * (uint32_t)TY;
   const int w = (int)(nx - x0 < 256u ? nx - x0 : 256u);
   const int hr = (int)(ny - r0 < (uint32_t)TY ? ny - r0 : (uint32_t)TY);
@@ -412,6 +410,15 @@ __global__ void __launch_bounds__(256) k_step2_d2(const T* __restrict__ g, T* __
       for (int i = 0; i < Q; ++i) st_at<T, NT>(h + i * (int64_t)n, s * S, f[i]);
     }
   }
+}
+
+template <typename T, int TY, bool NT, bool SAMPLE = false>
+__global__ void __launch_bounds__(256) k_step2_d2(const T* __restrict__ g, T* __restrict__ h,
+                                                  KParams<T> P, uint32_t step, int tiles_x,
+                                                  double* __restrict__ rowpart = nullptr,
+                                                  double* __restrict__ colpart = nullptr) {
+  step2_tile<T, TY, NT, SAMPLE>(g, h, P, step, blockIdx.x % (uint32_t)tiles_x, blockIdx.x / (uint32_t)tiles_x,
+                                rowpart, colpart);
 }
 
 // Column x of rows row0 .. row0 + RY - 1 (row0 is uniform over a wave).

@@ -46,12 +46,15 @@ def _alone(specs, precision, nsteps, t0):
 
 
 @pytest.mark.parametrize("precision", [4, 8])
-@pytest.mark.parametrize("use_graph,tiling", [(True, 0), (False, 0), (True, 1)])
-def test_batch_bit_identical_to_alone(precision, use_graph, tiling):
+@pytest.mark.parametrize("use_graph,tiling,depth,chunk", [(True, 0, 2, 16), (False, 0, 2, 16), (True, 1, 1, 16),
+                                                          (True, 0, 1, 16), (True, 0, 2, 7)])
+def test_batch_bit_identical_to_alone(precision, use_graph, tiling, depth, chunk):
+    # depth 2: D2Q5 members in two-step passes; odd chunks and remainders end
+    # with a single step
     specs = _specs()
-    nsteps, t0 = 37, 5           # 2 chunks of 16 + a remainder of 5
+    nsteps, t0 = 37, 5           # chunks of 16 (or 7) + a remainder
     ref = _alone(specs, precision, nsteps, t0)
-    B = flb.Batch(chunk=16, use_graph=use_graph, tiling=tiling)
+    B = flb.Batch(chunk=chunk, use_graph=use_graph, tiling=tiling, depth=depth)
     lats = []
     for spec in specs:
         f0, kw = _member(spec, precision)
