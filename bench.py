@@ -378,22 +378,29 @@ def bench_d3q7(torch, flb, inputs, tune, args):
             "mass_drift_rel": (m["mass"] - m["mass0"]) / m["mass0"]}
 
 
-def bench_batched(torch, flb, inputs, tune, args):
-    """1024 D1Q3 (L ~ U{64..4096}) + 256 D2Q5 (sides ~ U{128..1024}), FP32,
-    per-replica seed / omega / density, Poisson initial counts, 2000 steps."""
-    reps = inputs.ensemble(1024, 256, seed=0)
-    B = flb.Batch(chunk=16)
-    lats = []
+def ensemble_members(torch, flb, inputs):
+    """The ensemble's lattices with seeded Poisson initial counts (on the device)."""
     g = torch.Generator(device="cuda").manual_seed(0)
-    sites = 0
-    for r in reps:
+    lats = []
+    for r in inputs.ensemble(1024, 256, seed=0):
         w, _ = flb.constants(r["d"])
         L = flb.Lattice(r["d"], r["dims"], precision=4, omega=r["omega"], seed=r["seed"])
         shape = (len(w),) + tuple(reversed(r["dims"]))
         lam = torch.tensor(w * r["rho"], dtype=torch.float32, device="cuda").reshape((-1,) + (1,) * r["d"])
         L.set_populations(torch.poisson(lam.expand(shape).contiguous(), generator=g))
-        B.admit(L)
         lats.append(L)
+    return lats
+
+
+def bench_batched(torch, flb, inputs, tune, args):
+    """1024 D1Q3 (L ~ U{64..4096}) + 256 D2Q5 (sides ~ U{128..1024}), FP32,
+    per-replica seed / omega / density, Poisson initial counts, 2000 steps."""
+    bcfg = tune.batch_config()
+    B = flb.Batch(**bcfg)
+    lats = ensemble_members(torch, flb, inputs)
+    sites = 0
+    for L in lats:
+        B.admit(L)
         sites += L.nsite
     B.step(32)
     steps = 2000
@@ -404,7 +411,7 @@ def bench_batched(torch, flb, inputs, tune, args):
         L.close()
     B.close()
     return {"workload": "batched: 1024 D1Q3 L~U[64,4096] + 256 D2Q5 sides~U[128,1024], fp32, 2000 steps",
-            "replicas": len(reps), "sites": sites, "ms_per_step": round(ms, 4),
+            "batch_options": bcfg, "replicas": len(lats), "sites": sites, "ms_per_step": round(ms, 4),
             "mlups": round(sites / (ms * 1e-3) / 1e6, 1),
             "effective_gbs": round(bytes_step / (ms * 1e-3) / 1e9, 1)}
 

@@ -93,7 +93,7 @@ def finish_request(req):
 class Server:
     """Admission by HBM budget, continuous batching by ticks."""
 
-    def __init__(self, budget_bytes=None, tick_steps=64, chunk=16, use_graph=True, device=None):
+    def __init__(self, budget_bytes=None, tick_steps=64, chunk=None, use_graph=True, device=None):
         import torch
         self.torch = torch
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -103,7 +103,11 @@ class Server:
         self.budget = int(budget_bytes)
         self.used = 0
         self.tick_steps = int(tick_steps)
-        self.batch = flb.Batch(chunk=chunk, use_graph=use_graph)
+        from . import tune
+        bcfg = tune.batch_config()
+        if chunk is not None:
+            bcfg["chunk"] = chunk
+        self.batch = flb.Batch(use_graph=use_graph, **bcfg)
         self.queue = deque()
         self.active = []
         self.finished = []

@@ -115,3 +115,52 @@ def tune(d, precision, dims, steps=100, candidates=None, write=True, verbose=Tru
         with open(CACHE, "w") as fh:
             json.dump(cache, fh, indent=1, sort_keys=True)
     return best, results
+
+
+BATCH_DEFAULT = {"depth": 2, "tiling": 0, "chunk": 16}
+
+
+def batch_config():
+    """Options of flb.Batch for ensembles: the cached batch tuning result
+    (temporal-blocking depth of the D2Q5 members, work-item tiling, graph
+    chunk), or the defaults."""
+    ent = _load().get("batch")
+    return {k: int(ent[k]) for k in BATCH_DEFAULT} if ent else dict(BATCH_DEFAULT)
+
+
+def tune_batch(make_members, steps=400, depths=(1, 2), tilings=(0, 1), chunks=(8, 16, 32), write=True,
+               verbose=True):
+    """Time the batch options on the ensemble make_members() builds (a list
+    of lattices with their state set) and cache the fastest.  Members are
+    bit-identical under every option, so only the time decides."""
+    import torch
+    from . import flb
+
+    results = []
+    for depth in depths:
+        for tiling in tilings:
+            for chunk in chunks:
+                lats = make_members()
+                B = flb.Batch(chunk=chunk, tiling=tiling, depth=depth)
+                for L in lats:
+                    B.admit(L)
+                B.step(2 * chunk)
+                B.sync()
+                t0 = time.perf_counter()
+                B.step(steps)
+                B.sync()
+                ms = (time.perf_counter() - t0) * 1e3 / steps
+                for L in lats:
+                    B.retire(L)
+                    L.close()
+                B.close()
+                results.append(dict(depth=depth, tiling=tiling, chunk=chunk, ms=ms))
+                if verbose:
+                    print(f"[tune] batch depth={depth} tiling={tiling} chunk={chunk}: {ms * 1e3:.1f} us/step", flush=True)
+    best = min(results, key=lambda r: r["ms"])
+    if write:
+        cache = _load()
+        cache["batch"] = dict(best, when=time.strftime("%Y-%m-%d %H:%M"))
+        with open(CACHE, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+    return best, results
