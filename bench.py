@@ -417,13 +417,30 @@ def bench_batched(torch, flb, inputs, tune, args):
 
 
 def bench_served(torch, flb, inputs, tune, args):
+    """The configured stream (Poisson arrivals at 200 requests/s, about 250
+    times what one GPU serves, so latency is mostly queueing), then the same
+    requests arriving at 0.5 and 0.9 of the capacity that run measured
+    (site-updates per second over the mean work per request)."""
     from paper_1606_07801_amd import serve
-    reqs = serve.make_requests(args.requests, 200.0, seed=0)
-    S = serve.Server()
-    mk = S.run(reqs)
-    out = serve.summary(S, mk)
-    S.close()
-    out["workload"] = "served: Poisson arrivals 200/s, D1Q3/D2Q5/D3Q7, sites log-U[1e3,1e8], steps log-U[1e2,1e5], fp32"
+
+    def run(rate):
+        reqs = serve.make_requests(args.requests, rate, seed=0)
+        S = serve.Server()
+        mk = S.run(reqs, progress=30.0)
+        res = serve.summary(S, mk)
+        res["rate_per_s"] = round(rate, 4)
+        S.close()
+        return res, reqs
+
+    out, reqs = run(200.0)
+    cap = out["mlups"] * 1e6                                   # site-updates per second
+    mean_work = float(np.mean([r.sites * r.steps for r in reqs]))
+    out["workload"] = ("served: Poisson arrivals 200/s, D1Q3/D2Q5/D3Q7, sites log-U[1e3,1e8], "
+                       "steps log-U[1e2,1e5], fp32")
+    out["capacity_requests_per_s"] = round(cap / mean_work, 4)
+    for frac in (0.5, 0.9):
+        res, _ = run(frac * cap / mean_work)
+        out[f"at_{frac}_of_capacity"] = res
     return out
 
 

@@ -162,14 +162,21 @@ class Server:
                 self._retire(r, t)
         return n
 
-    def run(self, requests, clock=time.perf_counter):
+    def run(self, requests, clock=time.perf_counter, progress=0.0):
         """Serve `requests` (sorted by arrival time, seconds from now) until
-        all are finished.  Arrivals are released by the wall clock."""
+        all are finished.  Arrivals are released by the wall clock.  With
+        progress > 0 a status line goes to stderr every `progress` seconds."""
+        import sys
         t0 = clock()
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         for r in pending:
             r.arrival += t0
+        last = t0
         while pending or self.queue or self.active:
+            if progress > 0 and clock() - last >= progress:
+                last = clock()
+                print(f"[serve] t={last - t0:.0f}s finished {len(self.finished)}, active {len(self.active)}, "
+                      f"queued {len(self.queue)}, pending {len(pending)}", file=sys.stderr, flush=True)
             now = clock()
             while pending and pending[0].arrival <= now:
                 self.submit(pending.popleft())
