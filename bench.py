@@ -339,7 +339,32 @@ def bench_d1q3(torch, flb, inputs, tune, args):
             "mlups_unsampled": round(256 / ms_plain / 1e3, 2), "samples": n,
             "mass_drift": m["mass"] - m["mass0"], "mean_mass": sums["mass"] / n,
             "sk_mean_over_rho": round(float(S.mean() / (m["mass"] / 256)), 4),
-            "ms_per_step_one_launch_per_step": round(_d1q3_launch_per_step(torch, flb, f0, ks), 6)}
+            "ms_per_step_one_launch_per_step": round(_d1q3_launch_per_step(torch, flb, f0, ks), 6),
+            **({} if args.no_cpu_baseline else {"cpu_baseline": cpu_baseline_d1q3(flb, f0, cfg)})}
+
+
+def _scaled_err(g, ref, rho, w):
+    d = ref.ndim - 1
+    floor = rho * np.asarray(w).reshape((-1,) + (1,) * d)
+    return float((np.abs(np.asarray(g, dtype=np.float64) - ref) / np.maximum(np.abs(ref), floor)).max())
+
+
+def cpu_baseline_d1q3(flb, f0, cfg):
+    """The oracle on the whole D1Q3 workload (256 sites, 10^4 steps, one
+    core), and the GPU's final state against it (all populations)."""
+    import oracle
+    p = oracle.Params(d=1, omega_j=1.0, seed=0)
+    t0 = time.perf_counter()
+    ref = oracle.run(np.asarray(f0, dtype=np.float64), p, 10_000)
+    dt = time.perf_counter() - t0
+    L = flb.Lattice(1, (256,), precision=8, omega=1.0, seed=0, **cfg)
+    L.set_populations(f0)
+    L.step(10_000)
+    g = L.get_populations()
+    L.close()
+    return {"value": round(256 * 10_000 / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"the whole workload: 256 sites x 10^4 steps ({dt:.1f} s)",
+            "gpu_fp64_max_err_vs_oracle": _scaled_err(g, ref, 10.0, oracle.make_lattice(1).w)}
 
 
 def _d1q3_launch_per_step(torch, flb, f0, ks):
@@ -372,10 +397,43 @@ def bench_d3q7(torch, flb, inputs, tune, args):
     m = L.moments()
     L.close()
     gbs = 2 * 7 * 4 * N / (ms * 1e-3) / 1e9
-    return {"workload": "D3Q7 512^3 fp32 rho=5+sqrt(5)z, omega=1.2, 500 steps", "kernel": cfg,
-            "ms_per_step": round(ms, 4), "mlups": round(N / (ms * 1e-3) / 1e6, 1),
-            "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4),
-            "mass_drift_rel": (m["mass"] - m["mass0"]) / m["mass0"]}
+    out = {"workload": "D3Q7 512^3 fp32 rho=5+sqrt(5)z, omega=1.2, 500 steps", "kernel": cfg,
+           "ms_per_step": round(ms, 4), "mlups": round(N / (ms * 1e-3) / 1e6, 1),
+           "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4),
+           "mass_drift_rel": (m["mass"] - m["mass0"]) / m["mass0"]}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_d3q7(flb, inputs, cfg)
+    return out
+
+
+def cpu_baseline_d3q7(flb, inputs, cfg, nsample=2000):
+    """The oracle on a bounded sample of the D3Q7 workload: one step of
+    `nsample` sites from a seeded 512^3 Gaussian state (each site on its own
+    3 x 3 x 3 window), timed on one core; the GPU's step of the whole
+    lattice from the same state in the benchmark's launch configuration,
+    compared at those sites."""
+    import oracle
+    dims = (512, 512, 512)
+    lat = oracle.make_lattice(3)
+    rho = inputs.gaussian_field(dims, 5.0, np.sqrt(5.0), seed=0)
+    f0 = inputs.outer(lat.w, rho).astype(np.float32)
+    del rho
+    coords = inputs.rng(1).integers(0, 512, size=(nsample, 3))
+    p = oracle.Params(d=3, omega_j=1.2, seed=0)
+    t0 = time.perf_counter()
+    ref = oracle.run_sites(f0, lat, p, 0, 1, coords)
+    dt = time.perf_counter() - t0
+    L = flb.Lattice(3, dims, precision=4, omega=1.2, seed=0, **cfg)
+    L.set_populations(f0)
+    L.step(1)
+    g = L.get_populations()
+    L.close()
+    got = g[:, coords[:, 2], coords[:, 1], coords[:, 0]].astype(np.float64)
+    floor = 5.0 * lat.w[:, None]
+    err = float((np.abs(got - ref) / np.maximum(np.abs(ref), floor)).max())
+    return {"value": round(nsample / dt / 1e6, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"one step of {nsample} sampled sites of the 512^3 lattice ({dt:.1f} s)",
+            "gpu_fp32_max_err_vs_oracle": err}
 
 
 def ensemble_members(torch, flb, inputs):
@@ -410,10 +468,47 @@ def bench_batched(torch, flb, inputs, tune, args):
         B.retire(L)
         L.close()
     B.close()
-    return {"workload": "batched: 1024 D1Q3 L~U[64,4096] + 256 D2Q5 sides~U[128,1024], fp32, 2000 steps",
-            "batch_options": bcfg, "replicas": len(lats), "sites": sites, "ms_per_step": round(ms, 4),
-            "mlups": round(sites / (ms * 1e-3) / 1e6, 1),
-            "effective_gbs": round(bytes_step / (ms * 1e-3) / 1e9, 1)}
+    out = {"workload": "batched: 1024 D1Q3 L~U[64,4096] + 256 D2Q5 sides~U[128,1024], fp32, 2000 steps",
+           "batch_options": bcfg, "replicas": len(lats), "sites": sites, "ms_per_step": round(ms, 4),
+           "mlups": round(sites / (ms * 1e-3) / 1e6, 1),
+           "effective_gbs": round(bytes_step / (ms * 1e-3) / 1e9, 1)}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batched(flb, inputs, bcfg)
+    return out
+
+
+def cpu_baseline_batched(flb, inputs, bcfg, steps=100):
+    """The oracle on a bounded sample of the ensemble: the first two D1Q3 and
+    the first two D2Q5 replicas (seeded Poisson counts), `steps` steps each,
+    timed on one core; the same replicas run as a batch with the benchmark's
+    options, compared population by population."""
+    import oracle
+    reps = inputs.ensemble(1024, 256, seed=0)
+    pick = [r for r in reps if r["d"] == 1][:2] + [r for r in reps if r["d"] == 2][:2]
+    B = flb.Batch(**bcfg)
+    runs, dt, work, err = [], 0.0, 0, 0.0
+    for r in pick:
+        lat = oracle.make_lattice(r["d"])
+        f0 = inputs.poisson_counts(r["dims"], r["rho"] * lat.w, seed=r["seed"]).astype(np.float32)
+        L = flb.Lattice(r["d"], r["dims"], precision=4, omega=r["omega"], seed=r["seed"])
+        L.set_populations(f0)
+        B.admit(L)
+        runs.append((r, lat, f0, L))
+    B.step(steps)
+    B.sync()
+    for r, lat, f0, L in runs:
+        B.retire(L)
+        g = L.get_populations()
+        L.close()
+        t0 = time.perf_counter()
+        ref = oracle.run(f0.astype(np.float64), oracle.Params(d=r["d"], omega_j=r["omega"], seed=r["seed"]), steps)
+        dt += time.perf_counter() - t0
+        work += int(np.prod(r["dims"])) * steps
+        err = max(err, _scaled_err(g, ref, max(r["rho"], 1.0), lat.w))
+    B.close()
+    return {"value": round(work / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"2 D1Q3 + 2 D2Q5 replicas x {steps} steps ({dt:.1f} s)",
+            "gpu_fp32_max_err_vs_oracle": err}
 
 
 def bench_served(torch, flb, inputs, tune, args):
