@@ -81,7 +81,7 @@ def kernel_name(cfg):
     nt = "true" if cfg.get("nt_store") else "false"
     if cfg.get("kernel") == "two":
         ty = cfg.get("tile_rows") or 8
-        return f"flb::k_step2_d2<float, {2 if ty <= 2 else ty}, {nt}>"
+        return f"flb::k_step2_d2<float, {2 if ty <= 2 else ty}, {nt}, false>"
     if cfg.get("kernel") == "flat":
         return f"flb::k_step_flat<2, float, {cfg.get('tile_rows') or 2}, {nt}>"
     if cfg.get("kernel") == "plain":
