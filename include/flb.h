@@ -282,6 +282,16 @@ int flb_noise_sample(int32_t model, int32_t precision, int32_t law, uint64_t see
                      int64_t step, int64_t site0, int64_t nsite, void* d_words, void* d_vars,
                      void* hip_stream);
 
+/* The Gaussian map of the noise stream on given words, for checking it
+ * exhaustively: for j < n, with u_a = (2 (r_a >> 9) + 1) 2^-24 the uniform of
+ * word r_a = d_words[a * n + j] (a = 0, 1), write the Box-Muller pair
+ *   d_z[j] = sqrt(-2 ln u_0) cos(2 pi u_1),  d_z[n + j] = sqrt(-2 ln u_0) sin(2 pi u_1)
+ * in `precision` (4 or 8), computed exactly as the step kernels compute it
+ * (the paper's noise is Gaussian in the fluctuating-hydrodynamics limit;
+ * Sec. IV discusses the flat law it replaces).  d_words: 2 x n uint32,
+ * d_z: 2 x n reals, device pointers.  Asynchronous on hip_stream. */
+int flb_gauss_map(int32_t precision, const void* d_words, int64_t n, void* d_z, void* hip_stream);
+
 /* ---- batched ensembles (one launch advances many lattices) ---------------
  * A batch holds references to lattices created with flb_create (all float32
  * or all float64, all on one device).  flb_batch_step advances every member

@@ -1317,4 +1317,17 @@ int flb_noise_sample(int32_t model, int32_t precision, int32_t law, uint64_t see
   return FLB_OK;
 }
 
+int flb_gauss_map(int32_t precision, const void* d_words, int64_t n, void* d_z, void* hip_stream) {
+  if (precision != 4 && precision != 8) return fail(FLB_EINVAL, "precision must be 4 or 8");
+  if (n < 0) return fail(FLB_EINVAL, "negative size");
+  if (n == 0) return FLB_OK;
+  if (!d_words || !d_z) return fail(FLB_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  if (precision == 4) k_gauss_map<float><<<nb, 256, 0, st>>>((const uint32_t*)d_words, n, (float*)d_z);
+  else k_gauss_map<double><<<nb, 256, 0, st>>>((const uint32_t*)d_words, n, (double*)d_z);
+  HIP_TRY(hipGetLastError());
+  return FLB_OK;
+}
+
 }  // extern "C"

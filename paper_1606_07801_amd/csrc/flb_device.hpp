@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "flb_tables.hpp"
+
 // No implicit multiply-add contraction in the kernels: every kernel variant
 // (and every context a collision is inlined into) must round each site's
 // arithmetic identically, and which mul/add pairs the compiler fuses depends
@@ -78,23 +80,78 @@ __device__ __forceinline__ T word_to_uniform(uint32_t r) {
   return (T)((r >> 9) * 2u + 1u) * (T)5.9604644775390625e-08;  // 2^-24
 }
 
-// Box-Muller pair from two uniforms.
+// Box-Muller pair from two Philox words: with u0, u1 their uniforms,
+// z0 = R cos(2 pi u1), z1 = R sin(2 pi u1), R = sqrt(-2 ln u0).
+//
 // Float: the hardware instructions are used directly.  u0 and u1 lie in
 // [2^-24, 1), where v_log_f32 (base-2 logarithm) and v_sqrt_f32 are within
 // about one ulp and v_sin_f32 / v_cos_f32, which take their argument in
 // revolutions (sin 2 pi x), are within 1.3e-7 absolute (measured against
 // FP64 references over all odd multiples of 2^-25 in (0, 1)).  This keeps the
-// step's ALU cost below its memory cost; the double path uses the accurate
-// library functions.
-__device__ __forceinline__ void box_muller(float u0, float u1, float& z0, float& z1) {
+// step's ALU cost below its memory cost.
+__device__ __forceinline__ void gauss_pair(uint32_t r0, uint32_t r1, float& z0, float& z1) {
+  const float u0 = word_to_uniform<float>(r0), u1 = word_to_uniform<float>(r1);
   const float R = __builtin_amdgcn_sqrtf(-1.38629436111989061f * __builtin_amdgcn_logf(u0));  // -2 ln 2
   z0 = R * __builtin_amdgcn_cosf(u1);
   z1 = R * __builtin_amdgcn_sinf(u1);
 }
-__device__ __forceinline__ void box_muller(double u0, double u1, double& z0, double& z1) {
-  const double R = sqrt(-2.0 * log(u0));
+
+// Double: both functions take u = n 2^-24 with n odd in [1, 2^24) as the
+// integer n, which reduces their arguments exactly; a short series around a
+// tabulated breakpoint (flb_tables.hpp) finishes each.  Errors are a few ulp
+// of the result (the exhaustive GPU test over all 2^23 values of each
+// argument bounds them).
+
+// ln(n 2^-24), table-driven in the manner of Tang (ACM TOMS 16(4), 1990):
+// n 2^-24 = 2^-k m with m in [1/2, 1); the seven bits after n's leading one
+// select c_i = (257 + 2 i)/512, the middle of m's subinterval, and
+// ln(n 2^-24) = ln c_i + log1p(v) - k ln 2 with v = (m - c_i)/c_i, |v| <= 2^-8.
+// The last subinterval uses its right end c_127 = 1 (ln c = 0) and the top
+// binade (k = 0) has no ln 2 term, so values near u = 1 keep their relative
+// accuracy.
+__device__ __forceinline__ double ln_odd24(uint32_t n) {
+  const uint32_t k = (uint32_t)__builtin_clz(n) - 8u;
+  const uint32_t m = n << k;                                              // m 2^24, leading one at bit 23
+  const uint32_t i = (m >> 16) & (uint32_t)(kBmTab - 1);
+  const uint32_t c = i == (uint32_t)(kBmTab - 1) ? 512u : 257u + 2u * i;   // 512 c_i
+  const int32_t dm = (int32_t)m - (int32_t)(c << 15);                     // (m - c_i) 2^24, |dm| <= 2^16
+  const double2 t = kLnTab[i];
+  const double v = (double)dm * t.x;
+  // log1p(v) = v - v^2/2 + v^3/3 - ... - v^8/8; the rest is below 2^-75
+  double q = fma(v, -0.125, 1.0 / 7.0);
+  q = fma(v, q, -1.0 / 6.0);
+  q = fma(v, q, 0.2);
+  q = fma(v, q, -0.25);
+  q = fma(v, q, 1.0 / 3.0);
+  q = fma(v, q, -0.5);
+  const double lp = fma(v * v, q, v);
+  return fma(-(double)k, 0.69314718055994530942, t.y + lp);
+}
+
+// sin and cos of 2 pi n 2^-24: the top two bits of n give the quadrant, the
+// next seven the breakpoint phi_i = 2 pi (2 i + 1)/1024 and the last fifteen
+// the offset d = 2 pi (low15 - 2^14) 2^-24, |d| <= pi 2^-9.
+__device__ __forceinline__ void sincos_odd24(uint32_t n, double& s, double& c) {
+  const uint32_t quad = n >> 22;
+  const uint32_t i = (n >> 15) & (uint32_t)(kBmTab - 1);
+  const int32_t b = (int32_t)(n & 0x7FFFu) - 0x4000;
+  const double d = (double)b * 0x1.921fb54442d18p-22;                    // 2 pi 2^-24
+  const double d2 = d * d;
+  const double sd = fma(d * d2, fma(d2, 1.0 / 120.0, -1.0 / 6.0), d);     // sin d; next term < 2^-63
+  const double cm = d2 * fma(d2, fma(d2, -1.0 / 720.0, 1.0 / 24.0), -0.5);  // cos d - 1; next < 2^-74
+  const double2 t = kScTab[i];
+  const double S = fma(t.x, cm, fma(t.y, sd, t.x));                        // sin(phi_i + d)
+  const double C = fma(t.y, cm, fma(-t.x, sd, t.y));                       // cos(phi_i + d)
+  // quarter turns: (sin, cos) -> (cos, -sin) per quadrant
+  const double sv = (quad & 1u) ? C : S, cv = (quad & 1u) ? S : C;
+  s = (quad & 2u) ? -sv : sv;
+  c = ((quad + 1u) & 2u) ? -cv : cv;
+}
+
+__device__ __forceinline__ void gauss_pair(uint32_t r0, uint32_t r1, double& z0, double& z1) {
+  const double R = sqrt(-2.0 * ln_odd24(((r0 >> 9) << 1) | 1u));
   double s, c;
-  sincospi(2.0 * u1, &s, &c);
+  sincos_odd24(((r1 >> 9) << 1) | 1u, s, c);
   z0 = R * c;
   z1 = R * s;
 }
@@ -105,16 +162,14 @@ __device__ __forceinline__ void draw4(const KParams<T>& P, uint64_t site, uint32
                                       uint32_t block, T (&z)[4]) {
   uint32_t c0 = (uint32_t)site, c1 = (uint32_t)(site >> 32), c2 = step, c3 = block;
   philox4x32_10(c0, c1, c2, c3, P.k0, P.k1);
-  const T u0 = word_to_uniform<T>(c0), u1 = word_to_uniform<T>(c1);
-  const T u2 = word_to_uniform<T>(c2), u3 = word_to_uniform<T>(c3);
   if (P.law == kLawGauss) {
-    box_muller(u0, u1, z[0], z[1]);
-    box_muller(u2, u3, z[2], z[3]);
+    gauss_pair(c0, c1, z[0], z[1]);
+    gauss_pair(c2, c3, z[2], z[3]);
   } else {  // flat law on (-1, 1); the sqrt(3) lives in sq_*
-    z[0] = (T)2 * u0 - (T)1;
-    z[1] = (T)2 * u1 - (T)1;
-    z[2] = (T)2 * u2 - (T)1;
-    z[3] = (T)2 * u3 - (T)1;
+    z[0] = (T)2 * word_to_uniform<T>(c0) - (T)1;
+    z[1] = (T)2 * word_to_uniform<T>(c1) - (T)1;
+    z[2] = (T)2 * word_to_uniform<T>(c2) - (T)1;
+    z[3] = (T)2 * word_to_uniform<T>(c3) - (T)1;
   }
 }
 
@@ -170,14 +225,16 @@ struct Collide<1, T> {
   static constexpr int Q = 3;
   __device__ __forceinline__ static void run(T (&f)[3], const KParams<T>& P, uint64_t site,
                                              uint32_t step) {
+    // the variates depend on (site, step) only: drawn first, they overlap
+    // the loads of f still in flight
+    T z[4];
+    if (P.noise != kNoiseOff) draw4(P, site, step, 0u, z);
     const double rho_d = density_sum(f);
     const T rho = (T)rho_d;
     const T Mj = P.a * (f[1] - f[2]);
     const T Ms = fma(P.c1, f[1] + f[2], -(P.c0 * f[0]));
     T xj = 0, xs = 0;
     if (P.noise != kNoiseOff) {
-      T z[4];
-      draw4(P, site, step, 0u, z);
       const T sr = noise_scale(P, rho);
       xj = sr * P.sq_j * z[0];
       xs = sr * P.sq_s * z[1];
@@ -199,6 +256,8 @@ struct Collide<2, T> {
   static constexpr int Q = 5;
   __device__ __forceinline__ static void run(T (&f)[5], const KParams<T>& P, uint64_t site,
                                              uint32_t step) {
+    T z[4];
+    if (P.noise != kNoiseOff) draw4(P, site, step, 0u, z);  // independent of f: overlaps its loads
     const double rho_d = density_sum(f);
     const T rho = (T)rho_d;
     const T sx = f[1] + f[2], sy = f[3] + f[4];
@@ -208,8 +267,6 @@ struct Collide<2, T> {
     const T Ms = fma(P.c1, sx + sy, -(P.c0 * f[0]));
     T x1 = 0, x2 = 0, x3 = 0, x4 = 0;
     if (P.noise != kNoiseOff) {
-      T z[4];
-      draw4(P, site, step, 0u, z);
       const T sr = noise_scale(P, rho);
       const T gj = sr * P.sq_j;
       x1 = gj * z[0];
@@ -242,6 +299,11 @@ struct Collide<3, T> {
   static constexpr int Q = 7;
   __device__ __forceinline__ static void run(T (&f)[7], const KParams<T>& P, uint64_t site,
                                              uint32_t step) {
+    T z[4], zz[4];
+    if (P.noise != kNoiseOff) {  // independent of f: overlaps its loads
+      draw4(P, site, step, 0u, z);
+      draw4(P, site, step, 1u, zz);
+    }
     const double rho_d = density_sum(f);
     const T rho = (T)rho_d;
     const T sx = f[1] + f[2], sy = f[3] + f[4], sz = f[5] + f[6];
@@ -253,9 +315,6 @@ struct Collide<3, T> {
     const T Ms = fma(P.c1, (sx + sy) + sz, -(P.c0 * f[0]));
     T x[6] = {0, 0, 0, 0, 0, 0};
     if (P.noise != kNoiseOff) {
-      T z[4], zz[4];
-      draw4(P, site, step, 0u, z);
-      draw4(P, site, step, 1u, zz);
       const T sr = noise_scale(P, rho);
       const T gj = sr * P.sq_j, gn = sr * P.sq_n;
       x[0] = gj * z[0];

@@ -535,6 +535,18 @@ __global__ void k_from_canonical(const T* __restrict__ f, T* __restrict__ g, int
 }
 
 // ---------------------------------------------------------------------------
+// The Gaussian map alone, on given words (2 x n in, 2 x n out).
+template <typename T>
+__global__ void k_gauss_map(const uint32_t* __restrict__ words, int64_t n, T* __restrict__ z) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  T z0, z1;
+  gauss_pair(words[j], words[n + j], z0, z1);
+  z[j] = z0;
+  z[n + j] = z1;
+}
+
+// ---------------------------------------------------------------------------
 // Noise sampler: Philox words and the unit variates a step would use.
 template <int D, typename T>
 __global__ void k_noise_sample(KParams<T> P, uint32_t step, int64_t site0, int64_t nsite,

@@ -29,7 +29,7 @@ EXPORTS = (
     "flb_set_moment_sampling", "flb_sampled_moments", "flb_set_correlation",
     "flb_correlation", "flb_fourier_amplitudes", "flb_profile", "flb_set_regions", "flb_sync",
     "flb_destroy",
-    "flb_noise_sample", "flb_batch_create", "flb_batch_admit", "flb_batch_retire",
+    "flb_noise_sample", "flb_gauss_map", "flb_batch_create", "flb_batch_admit", "flb_batch_retire",
     "flb_batch_step", "flb_batch_size", "flb_batch_sync", "flb_batch_destroy",
 )
 
@@ -115,6 +115,7 @@ def load(path=LIB_PATH):
         "flb_sync": ([vp], ctypes.c_int),
         "flb_destroy": ([vp], ctypes.c_int),
         "flb_noise_sample": ([i32, i32, i32, u64, i64, i64, i64, vp, vp, vp], ctypes.c_int),
+        "flb_gauss_map": ([i32, vp, i64, vp, vp], ctypes.c_int),
         "flb_batch_create": ([ctypes.POINTER(BatchOpts), ctypes.POINTER(vp)], ctypes.c_int),
         "flb_batch_admit": ([vp, vp], ctypes.c_int),
         "flb_batch_retire": ([vp, vp], ctypes.c_int),
@@ -455,3 +456,23 @@ def noise_sample(model, seed, step, site0, nsite, precision=8, law="gauss", devi
                                   ctypes.c_void_p(st.cuda_stream)))
     st.synchronize()
     return words.cpu().numpy().view(np.uint32), var.cpu().numpy()
+
+
+def gauss_map(r0, r1, precision=8, device=None):
+    """The device Box-Muller map on Philox words r0, r1 (uint32 arrays of one
+    length): returns (sqrt(-2 ln u0) cos 2 pi u1, sqrt(-2 ln u0) sin 2 pi u1)
+    as the step kernels compute it."""
+    torch = _torch()
+    r0 = np.ascontiguousarray(r0, dtype=np.uint32)
+    r1 = np.ascontiguousarray(r1, dtype=np.uint32)
+    if r0.shape != r1.shape or r0.ndim != 1:
+        raise ValueError("r0 and r1 must be 1-D arrays of one length")
+    n = r0.size
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    words = torch.from_numpy(np.concatenate([r0, r1]).view(np.int32)).to(dev)
+    z = torch.empty((2, n), dtype=torch.float32 if precision == 4 else torch.float64, device=dev)
+    st = torch.cuda.current_stream(dev)
+    check(load().flb_gauss_map(int(precision), _ptr(words), int(n), _ptr(z), ctypes.c_void_p(st.cuda_stream)))
+    st.synchronize()
+    out = z.cpu().numpy()
+    return out[0], out[1]

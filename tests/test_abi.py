@@ -86,3 +86,12 @@ def test_extra_sizes_must_be_one():
     p.n[1] = 2
     with pytest.raises(flb.FlbError):
         flb.required_bytes(p)
+
+
+def test_gauss_map_validation_without_gpu():
+    lib = flb.load()
+    vp = ctypes.c_void_p
+    assert lib.flb_gauss_map(3, vp(8), 4, vp(8), None) == flb.FLB_EINVAL
+    assert lib.flb_gauss_map(8, vp(8), -1, vp(8), None) == flb.FLB_EINVAL
+    assert lib.flb_gauss_map(8, None, 4, vp(8), None) == flb.FLB_EINVAL
+    assert lib.flb_gauss_map(4, None, 0, None, None) == 0

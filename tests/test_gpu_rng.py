@@ -77,3 +77,40 @@ def test_oracle_philox_matches_rocrand_host_generator():
             assert np.array_equal(out, mine)
     finally:
         lib.rocrand_destroy_generator(gen)
+
+
+def test_gauss_map_exhaustive():
+    # every uniform u0 and every uniform u1 (2^23 values each; the low nine
+    # bits of a word do not enter), paired by a seeded permutation, against the
+    # oracle's Box-Muller in FP64 and, on a sample, against 40-digit values
+    gen = np.random.default_rng(17)
+    j = np.arange(1 << 23, dtype=np.uint32)
+    r0 = (j << np.uint32(9)) | gen.integers(0, 512, j.size, dtype=np.uint32)
+    r1 = (gen.permutation(j) << np.uint32(9)) | gen.integers(0, 512, j.size, dtype=np.uint32)
+    u0, u1 = philox.words_to_uniform(r0), philox.words_to_uniform(r1)
+    c_ref, s_ref = philox.box_muller(u0, u1)
+    R = np.sqrt(-2.0 * np.log(u0))
+    scale = np.maximum(1.0, R)
+    for prec, tol in ((8, 2e-15), (4, 1e-6)):
+        z0, z1 = flb.gauss_map(r0, r1, precision=prec)
+        e = max((np.abs(z0.astype(np.float64) - c_ref) / scale).max(),
+                (np.abs(z1.astype(np.float64) - s_ref) / scale).max())
+        print(f"[rng] gauss map fp{8 * prec}, all 2^23 u0 and u1: max |err| / max(1, R) = {e:.3e}", flush=True)
+        assert e <= tol
+        if prec == 8:
+            try:
+                import mpmath
+            except ImportError:
+                continue
+            mpmath.mp.dps = 40
+            pick = np.concatenate([gen.integers(0, j.size, 1500), np.argsort(u0)[:5], np.argsort(u0)[-5:],
+                                   np.argsort(u1)[:5], np.argsort(u1)[-5:]])
+            worst = 0.0
+            for t in pick:
+                a = mpmath.mpf(int(((int(r0[t]) >> 9) << 1) | 1)) / 2 ** 24
+                b = mpmath.mpf(int(((int(r1[t]) >> 9) << 1) | 1)) / 2 ** 24
+                rr = mpmath.sqrt(-2 * mpmath.log(a))
+                worst = max(worst, abs(float(rr * mpmath.cos(2 * mpmath.pi * b)) - z0[t]) / max(1.0, float(rr)),
+                            abs(float(rr * mpmath.sin(2 * mpmath.pi * b)) - z1[t]) / max(1.0, float(rr)))
+            print(f"[rng] gauss map fp64 vs 40-digit values: {worst:.3e}", flush=True)
+            assert worst <= 1e-15
