@@ -240,6 +240,17 @@ def main():
         P.close()
         out["fp64_plain"] = {"mlups": round(N / (ms64 * 1e-3) / 1e6, 1), "ms_per_step": round(ms64, 4),
                              "hbm_gbs": round(2 * Q * 8 * N / (kern64 * 1e-3) / 1e9, 1)}
+        # the tuned FP64 path (same state, same steps, no sampling)
+        cfg64 = tune.best_config(2, 8, dims)
+        P = flb.Lattice(2, dims, precision=8, omega=1.0, seed=0, **cfg64)
+        P.set_populations(f64)
+        P.step(10)
+        spl64 = steps_per_launch(cfg64)
+        ms64, kern64 = time_steps(torch, P, k64, 0, spl64)
+        P.close()
+        out["fp64_tuned"] = {"kernel": cfg64, "mlups": round(N / (ms64 * 1e-3) / 1e6, 1),
+                             "ms_per_step": round(ms64, 4),
+                             "effective_gbs": round(spl64 * 2 * Q * 8 * N / (kern64 * 1e-3) / 1e9, 1)}
 
     if args.copy_probe_mib:
         nb = args.copy_probe_mib << 20

@@ -341,23 +341,29 @@ bool resident_lds(const flb_lattice* h, size_t* lds, int* corr_lds) {
   return false;
 }
 
-template <int D, typename T, int SPT>
+template <int D, typename T, int SPT, int NT>
 void launch_resident_spt(flb_lattice* h, const ResArgs& A, size_t lds) {
   static bool attr = false;  // raise the dynamic LDS limit once per instantiation
   if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_resident<D, T, SPT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)k_resident<D, T, SPT, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               h->res_lds_max);
     (void)hipGetLastError();
     attr = true;
   }
-  k_resident<D, T, SPT><<<1, kResThreads, lds, h->stream>>>(make_kparams<T>(h->p, h->rho_eq), A);
+  k_resident<D, T, SPT, NT><<<1, NT, lds, h->stream>>>(make_kparams<T>(h->p, h->rho_eq), A);
 }
+
+// Up to kResSmall sites: four waves (one per SIMD) with up to four sites per
+// thread; beyond, sixteen waves.
+constexpr int kResSmall = 1024;
 
 template <int D, typename T>
 void launch_resident_t(flb_lattice* h, const ResArgs& A, size_t lds) {
-  if (h->n <= kResThreads) launch_resident_spt<D, T, 1>(h, A, lds);
-  else if (h->n <= 2 * kResThreads) launch_resident_spt<D, T, 2>(h, A, lds);
-  else launch_resident_spt<D, T, 4>(h, A, lds);
+  if (h->n <= 256) launch_resident_spt<D, T, 1, 256>(h, A, lds);
+  else if (h->n <= 512) launch_resident_spt<D, T, 2, 256>(h, A, lds);
+  else if (h->n <= kResSmall) launch_resident_spt<D, T, 4, 256>(h, A, lds);
+  else if (h->n <= 2 * kResThreads) launch_resident_spt<D, T, 2, kResThreads>(h, A, lds);
+  else launch_resident_spt<D, T, 4, kResThreads>(h, A, lds);
 }
 
 void launch_resident(flb_lattice* h, int c, size_t lds, int corr_lds) {

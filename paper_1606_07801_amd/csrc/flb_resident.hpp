@@ -1,6 +1,7 @@
 // A whole small lattice resident in one workgroup's LDS for many steps.
 //
-// One workgroup of 1024 threads loads the canonical state f_i(x, t) into LDS,
+// One workgroup (256 threads for up to 1024 sites, else 1024: fewer waves
+// make every barrier cheaper) loads the canonical state f_i(x, t) into LDS,
 // and for each step collides every site in registers (the per-site code of
 // the HBM kernels: same arithmetic, same noise stream, bit-identical
 // state), waits at a barrier and pushes the post-collision populations to
@@ -102,10 +103,11 @@ __device__ __forceinline__ double res_wave_sum(double v) {
   return ((res_lane(v, 0) + res_lane(v, 16)) + res_lane(v, 32)) + res_lane(v, 48);
 }
 
-// Largest power of two p <= cap with items * p <= kResThreads (at least 1).
+// Largest power of two p <= cap with items * p <= NT (at least 1).
+template <int NT>
 __device__ __forceinline__ int res_parts(int items, int cap) {
   int p = 1;
-  while (p * 2 <= cap && items * (p * 2) <= kResThreads) p *= 2;
+  while (p * 2 <= cap && items * (p * 2) <= NT) p *= 2;
   return p;
 }
 
@@ -136,8 +138,8 @@ struct ResMom {
 };
 
 // Adds this sample's lattice sums to mom (LDS, 40 slots).  Only waves that
-// hold sites reduce (site = tid + 1024 j, so wave w holds sites iff 64 w < N).
-template <int D, typename T, int SPT>
+// hold sites reduce (site = tid + NT j, so wave w holds sites iff 64 w < N).
+template <int D, typename T, int SPT, int NT>
 __device__ __forceinline__ void res_sample_moments(const T* st, int N, double* scr, double* mom,
                                                    const int (&sites)[SPT]) {
   using M = ResMom<D>;
@@ -169,7 +171,7 @@ __device__ __forceinline__ void res_sample_moments(const T* st, int N, double* s
     acc[3 + Q + M::NFF] += rho < 0 ? 1.0 : 0.0;
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nwa = (N + 63) / 64 < kResWaves ? (N + 63) / 64 : kResWaves;
+  const int nwa = (N + 63) / 64 < NT / 64 ? (N + 63) / 64 : NT / 64;
   if (wave < nwa) {
 #pragma unroll
     for (int v = 0; v < M::NV; ++v) {
@@ -189,10 +191,11 @@ __device__ __forceinline__ void res_sample_moments(const T* st, int N, double* s
 // In-place radix-2 FFT of a line: X (2 L doubles, complex) receives
 // sum_x (m[x] - mean) e^{-2 pi i k x / L} at index k.  L a power of two;
 // tw holds (cos, sin)(2 pi j / L).  Whole-workgroup barriers between stages.
+template <int NT>
 __device__ __forceinline__ void res_fft_line(double* X, const double* m, int L, double mean, const double* tw) {
   int lg = 0;
   while ((1 << lg) < L) ++lg;
-  for (int x = threadIdx.x; x < L; x += kResThreads) {
+  for (int x = threadIdx.x; x < L; x += NT) {
     const int r = (int)(__brev((unsigned)x) >> (32 - lg));
     X[2 * r] = m[x] - mean;
     X[2 * r + 1] = 0.0;
@@ -200,7 +203,7 @@ __device__ __forceinline__ void res_fft_line(double* X, const double* m, int L, 
   __syncthreads();
   for (int half = 1; half < L; half *= 2) {
     const int stride = L / (2 * half);
-    for (int b = threadIdx.x; b < L / 2; b += kResThreads) {
+    for (int b = threadIdx.x; b < L / 2; b += NT) {
       const int j = b & (half - 1);
       const int i0 = (b - j) * 2 + j, i1 = i0 + half;
       const double c = tw[2 * j * stride], sn = -tw[2 * j * stride + 1];
@@ -264,7 +267,7 @@ struct ResLocal {
   double *amp, *sij, *ct, *ring;  // LDS or HBM
 };
 
-template <int D, typename T, int SPT>
+template <int D, typename T, int SPT, int NT>
 __device__ __forceinline__ void res_sample_sk(const ResArgs& A, const ResLocal& R, const T* st, double* rho,
                                               double* marg, const double* tw, double* scr,
                                               const int (&sites)[SPT]) {
@@ -287,28 +290,28 @@ __device__ __forceinline__ void res_sample_sk(const ResArgs& A, const ResLocal& 
   if (lane == 0) scr[wave] = part;
   __syncthreads();
   double M = 0;
-  for (int w = 0; w < kResWaves; ++w) M += scr[w];
+  for (int w = 0; w < NT / 64; ++w) M += scr[w];
   const double mean = M / (double)N;
-  for (int e = threadIdx.x; e < ne; e += kResThreads)  // k = 0: the squared mass
+  for (int e = threadIdx.x; e < ne; e += NT)  // k = 0: the squared mass
     if (R.ent[e].x == -1) R.skl[e] += M * M / (double)N;
   double* mx = marg;
   double* my = marg + nx;
   double* mz = my + ny;
   __syncthreads();  // every thread has read the mass partials
   if constexpr (D >= 2) {  // axis marginals from rho, each a fixed-order sum
-    for (int x = threadIdx.x; x < nx; x += kResThreads) {
+    for (int x = threadIdx.x; x < nx; x += NT) {
       double a = 0;
       for (int r = 0; r < ny * nz; ++r) a += rho[r * nx + x];
       mx[x] = a;
     }
-    for (int y = threadIdx.x; y < ny; y += kResThreads) {
+    for (int y = threadIdx.x; y < ny; y += NT) {
       double a = 0;
       for (int z = 0; z < nz; ++z)
         for (int x = 0; x < nx; ++x) a += rho[(y + ny * z) * nx + x];
       my[y] = a;
     }
     if constexpr (D >= 3) {
-      for (int z = threadIdx.x; z < nz; z += kResThreads) {
+      for (int z = threadIdx.x; z < nz; z += NT) {
         double a = 0;
         for (int r = z * ny; r < (z + 1) * ny; ++r)
           for (int x = 0; x < nx; ++x) a += rho[r * nx + x];
@@ -323,8 +326,8 @@ __device__ __forceinline__ void res_sample_sk(const ResArgs& A, const ResLocal& 
     if (!(A.sk_fft & (1 << a))) continue;
     const int L = a == 0 ? nx : (a == 1 ? ny : nz);
     const double* m = D == 1 ? rho : (a == 0 ? mx : (a == 1 ? my : mz));
-    res_fft_line(scr, m, L, M / (double)L, tw + 2 * (a == 0 ? 0 : (a == 1 ? nx : nx + ny)));
-    for (int e = threadIdx.x; e < ne; e += kResThreads) {
+    res_fft_line<NT>(scr, m, L, M / (double)L, tw + 2 * (a == 0 ? 0 : (a == 1 ? nx : nx + ny)));
+    for (int e = threadIdx.x; e < ne; e += NT) {
       const int4 en = R.ent[e];
       if (en.x != a) continue;
       const int k = a == 0 ? en.y : (a == 1 ? en.z : en.w);
@@ -335,8 +338,8 @@ __device__ __forceinline__ void res_sample_sk(const ResArgs& A, const ResLocal& 
   if (!A.sk_dft) return;
   // the remaining entries: DFT of the marginal along one axis, or the direct
   // sum over the sites for a general wave vector
-  const int parts = res_parts(ne, 64);
-  for (int t = threadIdx.x; t < ne * parts; t += kResThreads) {
+  const int parts = res_parts<NT>(ne, 64);
+  for (int t = threadIdx.x; t < ne * parts; t += NT) {
     const int e = t / parts, p = t % parts;
     const int4 en = R.ent[e];
     double re = 0, im = 0;
@@ -362,7 +365,7 @@ __device__ __forceinline__ void res_sample_sk(const ResArgs& A, const ResLocal& 
     scr[2 * t + 1] = im;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < ne; e += kResThreads) {
+  for (int e = threadIdx.x; e < ne; e += NT) {
     const int4 en = R.ent[e];
     if (en.x == -1 || (en.x >= 0 && (A.sk_fft & (1 << en.x)))) continue;
     double re = 0, im = 0;
@@ -375,7 +378,7 @@ __device__ __forceinline__ void res_sample_sk(const ResArgs& A, const ResLocal& 
   __syncthreads();
 }
 
-template <int D, typename T>
+template <int D, typename T, int NT>
 __device__ __forceinline__ void res_sample_corr(const ResArgs& A, const ResLocal& R, const T* st,
                                                 const double* tw, double* scr, int64_t sidx, int rpos) {
   constexpr int Q = 2 * D + 1;
@@ -384,8 +387,8 @@ __device__ __forceinline__ void res_sample_corr(const ResArgs& A, const ResLocal
   const int items = nk * Q;
   // rows are split between parts (whole lines for the incremental phase),
   // except in 1-D where the single line is split
-  const int parts = res_parts(items, D == 1 ? 64 : (nrows < 64 ? nrows : 64));
-  for (int t = threadIdx.x; t < items * parts; t += kResThreads) {
+  const int parts = res_parts<NT>(items, D == 1 ? 64 : (nrows < 64 ? nrows : 64));
+  for (int t = threadIdx.x; t < items * parts; t += NT) {
     const int kk = t / (Q * parts), i = (t / parts) % Q, p = t % parts;
     const int4 kv = R.cki[kk];
     const T* fi = st + i * N;
@@ -424,7 +427,7 @@ __device__ __forceinline__ void res_sample_corr(const ResArgs& A, const ResLocal
   }
   __syncthreads();
   if (parts > 1) {
-    for (int u = threadIdx.x; u < items; u += kResThreads) {
+    for (int u = threadIdx.x; u < items; u += NT) {
       double re = 0, im = 0;
       for (int p = 0; p < parts; ++p) {
         re += scr[2 * (u * parts + p)];
@@ -441,7 +444,7 @@ __device__ __forceinline__ void res_sample_corr(const ResArgs& A, const ResLocal
   // nk nlag <= 2^20).
   const int nlag = A.nlag;
   const int ns = nk * Q * Q, nt = ns + nk * nlag;
-  for (int t = threadIdx.x; t < nt; t += kResThreads) {
+  for (int t = threadIdx.x; t < nt; t += NT) {
     if (t < ns) {
       const int k = t / (Q * Q), i = (t / Q) % Q, j = t % Q;
       const double* a = R.amp + k * 2 * Q;
@@ -482,8 +485,8 @@ __device__ __forceinline__ void res_sample_corr(const ResArgs& A, const ResLocal
   __syncthreads();
 }
 
-template <int D, typename T, int SPT>
-__global__ void __launch_bounds__(kResThreads) k_resident(KParams<T> P, ResArgs A) {
+template <int D, typename T, int SPT, int NT>
+__global__ void __launch_bounds__(NT) k_resident(KParams<T> P, ResArgs A) {
   constexpr int Q = 2 * D + 1;
   extern __shared__ __align__(16) unsigned char res_smem[];
   const int nx = A.nx, ny = A.ny, nz = A.nz;
@@ -515,9 +518,9 @@ __global__ void __launch_bounds__(kResThreads) k_resident(KParams<T> P, ResArgs 
     R.ring = A.ring;
   }
   const int tid = threadIdx.x;
-  for (int m = tid; m < 2 * lsum; m += kResThreads) tw[m] = A.tw[m];
-  for (int v = tid; v < kNV; v += kResThreads) R.mom[v] = 0.0;
-  for (int e = tid; e < ne; e += kResThreads) {
+  for (int m = tid; m < 2 * lsum; m += NT) tw[m] = A.tw[m];
+  for (int v = tid; v < kNV; v += NT) R.mom[v] = 0.0;
+  for (int e = tid; e < ne; e += NT) {
     R.skl[e] = 0.0;
     int4 en;
     if (e < A.nax) {
@@ -533,11 +536,11 @@ __global__ void __launch_bounds__(kResThreads) k_resident(KParams<T> P, ResArgs 
     }
     R.ent[e] = en;
   }
-  for (int k = tid; k < cnk; k += kResThreads)
+  for (int k = tid; k < cnk; k += NT)
     R.cki[k] = make_int4(A.ckinfo[3 * k], A.ckinfo[3 * k + 1], A.ckinfo[3 * k + 2], 0);
   if (A.corr_lds) {
-    for (int m = tid; m < nsij; m += kResThreads) R.sij[m] = A.sij[m];
-    for (int m = tid; m < nct; m += kResThreads) {
+    for (int m = tid; m < nsij; m += NT) R.sij[m] = A.sij[m];
+    for (int m = tid; m < nct; m += NT) {
       R.ct[m] = A.ct[m];
       R.ring[m] = A.ring[m];
     }
@@ -547,7 +550,7 @@ __global__ void __launch_bounds__(kResThreads) k_resident(KParams<T> P, ResArgs 
   int sites[SPT], cx[SPT], cy[SPT], cz[SPT];
 #pragma unroll
   for (int j = 0; j < SPT; ++j) {
-    const int s = tid + kResThreads * j;
+    const int s = tid + NT * j;
     sites[j] = s;
     cx[j] = s % nx;
     cy[j] = (s / nx) % ny;
@@ -572,16 +575,16 @@ __global__ void __launch_bounds__(kResThreads) k_resident(KParams<T> P, ResArgs 
   for (int k = 0; k < A.nsteps; ++k) {
     const int64_t t = A.step0 + k;
     if (cm == 0) {
-      res_sample_moments<D, T, SPT>(st, N, scr, R.mom, sites);
+      res_sample_moments<D, T, SPT, NT>(st, N, scr, R.mom, sites);
       cm = A.mom_every;
     }
     if (cc == 0) {
-      res_sample_corr<D, T>(A, R, st, tw, scr, csamp++, rpos);
+      res_sample_corr<D, T, NT>(A, R, st, tw, scr, csamp++, rpos);
       rpos = rpos + 1 == A.nlag ? 0 : rpos + 1;
       cc = A.corr_every;
     }
     if (cs == 0) {
-      res_sample_sk<D, T, SPT>(A, R, st, rho, marg, tw, scr, sites);
+      res_sample_sk<D, T, SPT, NT>(A, R, st, rho, marg, tw, scr, sites);
       cs = A.sk_every;
     }
     --cm;
@@ -631,11 +634,11 @@ __global__ void __launch_bounds__(kResThreads) k_resident(KParams<T> P, ResArgs 
   }
   // flush this launch's sums
   if (A.mom_every > 0)
-    for (int v = tid; v < kNV; v += kResThreads) A.momacc[v] += R.mom[v];
-  for (int e = tid; e < ne; e += kResThreads) A.skacc[R.eslot[e]] += R.skl[e];
+    for (int v = tid; v < kNV; v += NT) A.momacc[v] += R.mom[v];
+  for (int e = tid; e < ne; e += NT) A.skacc[R.eslot[e]] += R.skl[e];
   if (A.corr_lds) {
-    for (int m = tid; m < nsij; m += kResThreads) A.sij[m] = R.sij[m];
-    for (int m = tid; m < nct; m += kResThreads) {
+    for (int m = tid; m < nsij; m += NT) A.sij[m] = R.sij[m];
+    for (int m = tid; m < nct; m += NT) {
       A.ct[m] = R.ct[m];
       A.ring[m] = R.ring[m];
     }
