@@ -507,6 +507,7 @@ def cpu_baseline_batched(flb, inputs, bcfg, steps=100):
         runs.append((r, lat, f0, L))
     B.step(steps)
     B.sync()
+    per = []
     for r, lat, f0, L in runs:
         B.retire(L)
         g = L.get_populations()
@@ -515,11 +516,16 @@ def cpu_baseline_batched(flb, inputs, bcfg, steps=100):
         ref = oracle.run(f0.astype(np.float64), oracle.Params(d=r["d"], omega_j=r["omega"], seed=r["seed"]), steps)
         dt += time.perf_counter() - t0
         work += int(np.prod(r["dims"])) * steps
-        err = max(err, _scaled_err(g, ref, max(r["rho"], 1.0), lat.w))
+        e = _scaled_err(g, ref, max(r["rho"], 1.0), lat.w)
+        err = max(err, e)
+        # below a few particles per site FP32 rounding reaches the noise
+        # amplitude sqrt(max(rho, 0)) as sqrt(rounding), so the trajectories
+        # separate over many steps; the error is reported with the density
+        per.append({"d": r["d"], "dims": list(r["dims"]), "rho": round(r["rho"], 3), "max_err": e})
     B.close()
     return {"value": round(work / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"2 D1Q3 + 2 D2Q5 replicas x {steps} steps ({dt:.1f} s)",
-            "gpu_fp32_max_err_vs_oracle": err}
+            "gpu_fp32_max_err_vs_oracle": err, "per_replica": per}
 
 
 def bench_served(torch, flb, inputs, tune, args):
