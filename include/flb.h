@@ -277,7 +277,7 @@ int flb_destroy(flb_lattice* h);
  * write the Philox words (uint32, nblock x 4 x nsite, nblock = 1 for D1Q3 and
  * D2Q5 and 2 for D3Q7) to d_words and the Q - 1 unit-variance variates of
  * `law` (Q - 1 x nsite, of `precision`) to d_vars.  Device pointers; either
- * may be NULL.  Asynchronous on hip_stream. */
+ * may be NULL.  nsite <= 2^31 - 256.  Asynchronous on hip_stream. */
 int flb_noise_sample(int32_t model, int32_t precision, int32_t law, uint64_t seed,
                      int64_t step, int64_t site0, int64_t nsite, void* d_words, void* d_vars,
                      void* hip_stream);
@@ -289,7 +289,8 @@ int flb_noise_sample(int32_t model, int32_t precision, int32_t law, uint64_t see
  * in `precision` (4 or 8), computed exactly as the step kernels compute it
  * (the paper's noise is Gaussian in the fluctuating-hydrodynamics limit;
  * Sec. IV discusses the flat law it replaces).  d_words: 2 x n uint32,
- * d_z: 2 x n reals, device pointers.  Asynchronous on hip_stream. */
+ * d_z: 2 x n reals, device pointers; n <= 2^31 - 256.  Asynchronous on
+ * hip_stream. */
 int flb_gauss_map(int32_t precision, const void* d_words, int64_t n, void* d_z, void* hip_stream);
 
 /* ---- batched ensembles (one launch advances many lattices) ---------------

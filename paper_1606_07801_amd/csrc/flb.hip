@@ -1288,12 +1288,16 @@ int flb_sync(flb_lattice* h) {
   return FLB_OK;
 }
 
+// one thread per value, 256 per block: the grid stays below 2^23 blocks
+constexpr int64_t kMaxSample = (1ll << 31) - 256;
+
 int flb_noise_sample(int32_t model, int32_t precision, int32_t law, uint64_t seed, int64_t step,
                      int64_t site0, int64_t nsite, void* d_words, void* d_vars, void* hip_stream) {
   if (model < 1 || model > 3) return fail(FLB_EINVAL, "model must be 1, 2 or 3");
   if (precision != 4 && precision != 8) return fail(FLB_EINVAL, "precision must be 4 or 8");
   if (law < 0 || law > 1) return fail(FLB_EINVAL, "law must be 0 or 1");
   if (nsite < 0 || site0 < 0 || step < 0) return fail(FLB_EINVAL, "negative size, site or step");
+  if (nsite > kMaxSample) return fail(FLB_EINVAL, "nsite above 2^31 - 256");
   if (nsite == 0) return FLB_OK;
   flb_params p{};
   p.model = model;
@@ -1326,6 +1330,7 @@ int flb_noise_sample(int32_t model, int32_t precision, int32_t law, uint64_t see
 int flb_gauss_map(int32_t precision, const void* d_words, int64_t n, void* d_z, void* hip_stream) {
   if (precision != 4 && precision != 8) return fail(FLB_EINVAL, "precision must be 4 or 8");
   if (n < 0) return fail(FLB_EINVAL, "negative size");
+  if (n > kMaxSample) return fail(FLB_EINVAL, "n above 2^31 - 256");
   if (n == 0) return FLB_OK;
   if (!d_words || !d_z) return fail(FLB_EINVAL, "NULL argument");
   hipStream_t st = (hipStream_t)hip_stream;

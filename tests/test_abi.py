@@ -95,3 +95,11 @@ def test_gauss_map_validation_without_gpu():
     assert lib.flb_gauss_map(8, vp(8), -1, vp(8), None) == flb.FLB_EINVAL
     assert lib.flb_gauss_map(8, None, 4, vp(8), None) == flb.FLB_EINVAL
     assert lib.flb_gauss_map(4, None, 0, None, None) == 0
+
+
+def test_sample_size_bounds_without_gpu():
+    lib = flb.load()
+    vp = ctypes.c_void_p
+    assert lib.flb_gauss_map(8, vp(8), 1 << 31, vp(8), None) == flb.FLB_EINVAL
+    assert lib.flb_noise_sample(2, 8, 0, 1, 0, 0, 1 << 31, None, None, None) == flb.FLB_EINVAL
+    assert lib.flb_noise_sample(2, 8, 0, 1, 0, 0, 0, None, None, None) == 0
