@@ -585,7 +585,8 @@ void classify_k(const flb_lattice* h, const int32_t* kvec, int nk, KStage* st, i
 }
 
 // Axis marginals from rowsum / colpart (nchunk chunks), then the axis DFTs.
-void axis_sk(flb_lattice* h, int set, int64_t nchunk) {
+// mx_ready: the x marginal is already in place (k_axis_reduce).
+void axis_sk(flb_lattice* h, int set, int64_t nchunk, bool mx_ready) {
   const int64_t nx = h->p.n[0], ny = h->p.n[1], nz = h->p.n[2];
   hipStream_t st = h->stream;
   char* w = h->work;
@@ -595,14 +596,16 @@ void axis_sk(flb_lattice* h, int set, int64_t nchunk) {
   double* my = mx + nx;
   double* mz = my + ny;
   const double* tw = (const double*)(w + h->wl.tw);
-  k_marginal_x<<<(unsigned)((nx + 63) / 64), 256, 0, st>>>(colpart, nchunk, nx, mx);
-  k_marginal_y<<<(unsigned)((ny + 255) / 256), 256, 0, st>>>(rowsum, ny, nz, my);
+  if (!mx_ready) k_marginal_x<<<(unsigned)((nx + 63) / 64), 256, 0, st>>>(colpart, nchunk, nx, mx);
+  // with one plane the row sums are the y marginal
+  if (nz > 1) k_marginal_y<<<(unsigned)((ny + 255) / 256), 256, 0, st>>>(rowsum, ny, nz, my);
   if (h->d == 3) k_marginal_z<<<(unsigned)nz, 256, 0, st>>>(rowsum, ny, mz);
-  k_sk_axis<<<(unsigned)h->nax[set], 256, 0, st>>>(mx, my, mz, nx, ny, nz,
-                                                   (const int64_t*)(w + h->wl.kinfo[set]),
-                                                   (const int32_t*)(w + h->wl.slot_ax[set]), tw,
-                                                   tw + 2 * nx, tw + 2 * (nx + ny),
-                                                   (double*)(w + h->wl.sval[set]));
+  // an axis-only accumulator list is accumulated here (sk_accumulate skips it)
+  double* acc = set == 1 && h->ngen[1] == 0 ? (double*)(w + h->wl.skacc) : nullptr;
+  k_sk_axis<<<(unsigned)((h->nax[set] + kSkAxisK - 1) / kSkAxisK), kSkAxisThreads, 0, st>>>(
+      mx, nz > 1 ? my : rowsum, mz, nx, ny, nz, (const int64_t*)(w + h->wl.kinfo[set]),
+      (const int32_t*)(w + h->wl.slot_ax[set]), h->nax[set], tw, tw + 2 * nx, tw + 2 * (nx + ny),
+      (double*)(w + h->wl.sval[set]), acc);
 }
 
 // S(k) of the current state for k-list `set`.  from_step: the axis
@@ -621,17 +624,18 @@ void launch_sk_t(flb_lattice* h, int set, bool from_step) {
     const int64_t rpc = (nrows + nchunk - 1) / nchunk;
     double* rowsum = (double*)(w + h->wl.rowsum);
     double* colpart = (double*)(w + h->wl.colpart);
-    if (from_step) {
+    static_assert(kColChunks <= 64, "k_axis_reduce holds at most 64 group sums per column");
+    if (from_step) {  // row sums and the x marginal from the pass's partials, one launch
       const int64_t ntx = (nx + 255) / 256, ntr = (nrows + kSampleRows - 1) / kSampleRows;
-      k_rowpart_reduce<<<(unsigned)((nrows + 255) / 256), 256, 0, st>>>((const double*)(w + h->wl.rowpart), ntx, nrows, rowsum);
-      k_colpart_reduce<<<dim3((unsigned)((nx + 255) / 256), (unsigned)nchunk), 256, 0, st>>>(
-          (const double*)(w + h->wl.colbig), ntr, nx, nchunk, colpart);
-    }
-    if (!from_step) {
+      const int64_t nblk = (nx + 15) / 16 + (nrows + 1023) / 1024;
+      k_axis_reduce<<<(unsigned)nblk, 1024, 0, st>>>((const double*)(w + h->wl.rowpart), ntx, nrows, rowsum,
+                                                    (const double*)(w + h->wl.colbig), ntr, nx, nchunk,
+                                                    (double*)(w + h->wl.marg));
+    } else {
       k_row_sums<D, T><<<(unsigned)nrows, 256, 0, st>>>(g, nx, ny, nz, rowsum);
       k_col_partial<D, T><<<dim3((unsigned)((nx + 255) / 256), (unsigned)nchunk), 256, 0, st>>>(g, nx, ny, nz, rpc, colpart);
     }
-    axis_sk(h, set, nchunk);
+    axis_sk(h, set, nchunk, from_step);
   }
   if (h->ngen[set] > 0 && !from_step) {
     const int64_t nchunk = std::min<int64_t>(kSkChunks, (h->n + 255) / 256);
@@ -678,10 +682,13 @@ void launch_step_sampled(flb_lattice* h, const void* g, void* out, uint32_t step
   }
 }
 
+// Adds the last sample of k-list 1 to the accumulator (an axis-only list
+// was added by k_sk_axis already).
 void sk_accumulate(flb_lattice* h) {
   char* w = h->work;
-  k_sk_accumulate<<<(h->nk[1] + 255) / 256, 256, 0, h->stream>>>((const double*)(w + h->wl.sval[1]),
-                                                                 (double*)(w + h->wl.skacc), h->nk[1]);
+  if (h->ngen[1] > 0)
+    k_sk_accumulate<<<(h->nk[1] + 255) / 256, 256, 0, h->stream>>>((const double*)(w + h->wl.sval[1]),
+                                                                   (double*)(w + h->wl.skacc), h->nk[1]);
   h->sk_count += 1;
 }
 

@@ -183,27 +183,51 @@ __global__ void k_marginal_y(const double* __restrict__ rowsum, int64_t ny, int6
   my[y] = acc;
 }
 
-// out[g][x] = sum of in[c][x] over the chunks c of group g (groups of
-// consecutive chunks, in order): shrinks many column partials to ngroup.
-__global__ void k_colpart_reduce(const double* __restrict__ in, int64_t nchunk, int64_t nx,
-                                 int64_t ngroup, double* __restrict__ out) {
-  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t g = blockIdx.y;
-  if (x >= nx) return;
-  const int64_t c0 = g * nchunk / ngroup, c1 = (g + 1) * nchunk / ngroup;
-  double acc = 0;
-  for (int64_t c = c0; c < c1; ++c) acc += in[c * nx + x];
-  out[g * nx + x] = acc;
-}
-
-// rowsum[row] = sum over x tiles of rowpart[t][row].
-__global__ void k_rowpart_reduce(const double* __restrict__ rowpart, int64_t ntx, int64_t nrows,
-                                 double* __restrict__ rowsum) {
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= nrows) return;
-  double acc = 0;
-  for (int64_t t = 0; t < ntx; ++t) acc += rowpart[t * nrows + row];
-  rowsum[row] = acc;
+// The reductions after a sampled pass, in one launch of 1024-thread blocks.
+// Blocks [0, ncb), ncb = ceil(nx / 16), build the x marginal of 16 columns
+// straight from the per-tile column partials: thread (g, c) adds the tiles
+// of group g (ngroup <= 64 groups of consecutive tiles) for column c in
+// order; then, per column, 4 interleaved subsets of the group sums are each
+// added in order and combined in order (the additions of a group reduction
+// followed by k_marginal_x).  The other blocks: rowsum[row] = sum over the x
+// tiles of rowpart[t][row], in order.
+__global__ void __launch_bounds__(1024) k_axis_reduce(const double* __restrict__ rowpart, int64_t ntx,
+                                                      int64_t nrows, double* __restrict__ rowsum,
+                                                      const double* __restrict__ colbig, int64_t ntr,
+                                                      int64_t nx, int64_t ngroup, double* __restrict__ mx) {
+  const int64_t ncb = (nx + 15) / 16;
+  if ((int64_t)blockIdx.x >= ncb) {
+    const int64_t row = ((int64_t)blockIdx.x - ncb) * blockDim.x + threadIdx.x;
+    if (row >= nrows) return;
+    double acc = 0;
+#pragma unroll 8
+    for (int64_t t = 0; t < ntx; ++t) acc += rowpart[t * nrows + row];
+    rowsum[row] = acc;
+    return;
+  }
+  __shared__ double gs[64][16];
+  __shared__ double ps[4][16];
+  const int c = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int64_t x = (int64_t)blockIdx.x * 16 + c;
+  if (g < ngroup && x < nx) {
+    const int64_t t0 = g * ntr / ngroup, t1 = (g + 1) * ntr / ngroup;
+    double a = 0;
+#pragma unroll 8
+    for (int64_t t = t0; t < t1; ++t) a += colbig[t * nx + x];
+    gs[g][c] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int cc = threadIdx.x & 15, sub = threadIdx.x >> 4;
+    double acc = 0;
+    for (int gg = sub; gg < ngroup; gg += 4) acc += gs[gg][cc];
+    ps[sub][cc] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    const int64_t xx = (int64_t)blockIdx.x * 16 + threadIdx.x;
+    if (xx < nx) mx[xx] = ((ps[0][threadIdx.x] + ps[1][threadIdx.x]) + ps[2][threadIdx.x]) + ps[3][threadIdx.x];
+  }
 }
 
 // Twiddles of one axis: tw[2p] = cos(2 pi p / L), tw[2p + 1] = sin(2 pi p / L).
@@ -227,51 +251,123 @@ __global__ void __launch_bounds__(256) k_marginal_z(const double* __restrict__ r
   if (threadIdx.x == 0) mz[z] = acc;
 }
 
-// Axis structure factor from a marginal: one block per wave vector; the
-// twiddles come from a table of the axis (k_twiddle).
-// kinfo[j] = (axis, k mod L_axis); axis < 0 marks a k = 0 entry.
-// S = |sum_x (m(x) - mean) e^{-2 pi i k x / L}|^2 / N; k = 0 gives M^2 / N.
-__global__ void __launch_bounds__(256) k_sk_axis(const double* __restrict__ mx,
+// Axis structure factor from the marginals: each block takes kSkAxisK
+// consecutive entries of the axis list; kinfo[j] = (axis, k mod L_axis),
+// axis < 0 marking a k = 0 entry.
+//   S = |sum_x (m(x) - mean) e^{-2 pi i k x / L}|^2 / N,  k = 0: M^2 / N,
+// with M the mass (the sum of the x marginal) and mean = M / L of the
+// entry's axis.  Each thread takes a contiguous run of x: the twiddle of its
+// first x comes from the axis table (integer phase k x mod L), each next one
+// by a rotation with the twiddle of k, reloaded from the table every 64
+// steps (rounding stays at a few ulp); the block's entries share the loads
+// of the marginal.  With acc given, S is also added to acc at its slot (the
+// accumulator update of an axis-only k-list, without a launch of its own).
+constexpr int kSkAxisK = 4;
+constexpr int kSkAxisThreads = 256;
+
+__global__ void __launch_bounds__(kSkAxisThreads) k_sk_axis(const double* __restrict__ mx,
                                                  const double* __restrict__ my,
                                                  const double* __restrict__ mz, int64_t nx,
                                                  int64_t ny, int64_t nz,
                                                  const int64_t* __restrict__ kinfo,
-                                                 const int32_t* __restrict__ slot,
+                                                 const int32_t* __restrict__ slot, int nax,
                                                  const double* __restrict__ twx,
                                                  const double* __restrict__ twy,
                                                  const double* __restrict__ twz,
-                                                 double* __restrict__ sval) {
-  __shared__ double lds[4];
-  const int j = blockIdx.x;
-  const int64_t axis = kinfo[2 * j], k = kinfo[2 * j + 1];
+                                                 double* __restrict__ sval,
+                                                 double* __restrict__ acc) {
+  constexpr int K = kSkAxisK, NW = kSkAxisThreads / 64;
+  __shared__ double mass_w[NW];
+  __shared__ double red[2 * K][NW];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j0 = blockIdx.x * K;
   const double N = (double)(nx * ny * nz);
-  const double* m = axis == 1 ? my : (axis == 2 ? mz : mx);
-  const double* tw = axis == 1 ? twy : (axis == 2 ? twz : twx);
-  const int64_t L = axis == 1 ? ny : (axis == 2 ? nz : nx);
-  // mass from the chosen marginal
   double tot = 0;
-  for (int64_t x = threadIdx.x; x < L; x += blockDim.x) tot += m[x];
-  tot = block_sum256(tot, lds);
-  __shared__ double mean_s;
-  if (threadIdx.x == 0) mean_s = tot / (double)L;
+#pragma unroll 4
+  for (int64_t x = threadIdx.x; x < nx; x += blockDim.x) tot += mx[x];
+  tot = wave_sum(tot);
+  if (lane == 0) mass_w[wave] = tot;
   __syncthreads();
-  const double mean = mean_s;
-  if (axis < 0) {
-    if (threadIdx.x == 0) sval[slot[j]] = tot * tot / N;
-    return;
+  double M = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) M += mass_w[w];
+  int ax[K];
+  int64_t kk[K];
+  double re[K], im[K];
+#pragma unroll
+  for (int e = 0; e < K; ++e) {
+    const int j = j0 + e;
+    ax[e] = j < nax ? (int)kinfo[2 * j] : -2;
+    kk[e] = j < nax ? kinfo[2 * j + 1] : 0;
+    re[e] = 0.0;
+    im[e] = 0.0;
   }
-  double re = 0, im = 0;
-  for (int64_t x = threadIdx.x; x < L; x += blockDim.x) {
-    const int64_t p = (k * x) % L;  // integer phase
-    const double c = tw[2 * p], s = tw[2 * p + 1];
-    const double v = m[x] - mean;
-    re += v * c;
-    im -= v * s;
+  for (int a = 0; a < 3; ++a) {
+    bool any = false;
+#pragma unroll
+    for (int e = 0; e < K; ++e) any |= ax[e] == a;
+    if (!any) continue;  // uniform over the block
+    const double* m = a == 0 ? mx : (a == 1 ? my : mz);
+    const double* tw = a == 0 ? twx : (a == 1 ? twy : twz);
+    const int64_t L = a == 0 ? nx : (a == 1 ? ny : nz);
+    const double mean = M / (double)L;
+    const int64_t C = (L + blockDim.x - 1) / blockDim.x;
+    const int64_t x0 = (int64_t)threadIdx.x * C, x1 = x0 + C < L ? x0 + C : L;
+    double sr[K], si[K];
+#pragma unroll
+    for (int e = 0; e < K; ++e) {  // (entries of other axes read entry 0 and ignore it)
+      const int64_t q = ax[e] == a ? kk[e] : 0;
+      sr[e] = tw[2 * q];
+      si[e] = tw[2 * q + 1];
+    }
+    for (int64_t xa = x0; xa < x1; xa += 64) {
+      double wr[K], wi[K];
+#pragma unroll
+      for (int e = 0; e < K; ++e) {
+        const int64_t p = L < (1ll << 31) ? (kk[e] * xa) % L
+                                          : (int64_t)((unsigned __int128)kk[e] * (uint64_t)xa % (uint64_t)L);
+        wr[e] = tw[2 * p];  // p < L: in the table for every entry
+        wi[e] = tw[2 * p + 1];
+      }
+      const int64_t xb = xa + 64 < x1 ? xa + 64 : x1;
+#pragma unroll 8
+      for (int64_t x = xa; x < xb; ++x) {  // (unrolled: the loads of m issue together)
+        const double v = m[x] - mean;
+#pragma unroll
+        for (int e = 0; e < K; ++e) {
+          if (ax[e] != a) continue;
+          re[e] += v * wr[e];
+          im[e] -= v * wi[e];
+          const double nr = wr[e] * sr[e] - wi[e] * si[e];
+          wi[e] = wr[e] * si[e] + wi[e] * sr[e];
+          wr[e] = nr;
+        }
+      }
+    }
   }
-  re = block_sum256(re, lds);
+  // block sums of the K pairs: wave sums, then the waves in order
+#pragma unroll
+  for (int e = 0; e < K; ++e) {
+    const double r = wave_sum(re[e]), i = wave_sum(im[e]);
+    if (lane == 0) {
+      red[2 * e][wave] = r;
+      red[2 * e + 1][wave] = i;
+    }
+  }
   __syncthreads();
-  im = block_sum256(im, lds);
-  if (threadIdx.x == 0) sval[slot[j]] = (re * re + im * im) / N;
+  if (threadIdx.x < K) {
+    const int e = threadIdx.x, j = j0 + e;
+    if (j < nax) {
+      double r = 0, i = 0;
+      for (int w = 0; w < NW; ++w) {
+        r += red[2 * e][w];
+        i += red[2 * e + 1][w];
+      }
+      const double S = kinfo[2 * j] < 0 ? M * M / N : (r * r + i * i) / N;
+      sval[slot[j]] = S;
+      if (acc) acc[slot[j]] += S;
+    }
+  }
 }
 
 // General wave vectors: direct sum over sites.  Block (c, j) sums the sites
