@@ -283,6 +283,35 @@ __device__ __forceinline__ void flat_tile(const T* __restrict__ g, T* __restrict
   }
 }
 
+// Sum over the 64 lanes of a wave with DPP lane moves (no LDS): quad swaps,
+// half-row and row mirrors leave every lane with its 16-lane row sum (the
+// same bits in all 16 lanes, the additions being commutative pairwise); the
+// four row sums are read from lanes 0, 16, 32, 48 and added in that order.
+// A fixed order, so the result does not depend on scheduling; all 64 lanes
+// must be active.  The result is uniform across the wave.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double wave_sum_fixed(double v) {
+  v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x140>(v);  // row_mirror
+  return ((lane_value(v, 0) + lane_value(v, 16)) + lane_value(v, 32)) + lane_value(v, 48);
+}
+
 // Two D2Q5 steps per pass (temporal blocking).  A workgroup owns the
 // columns x0 .. x0 + w - 1 (w <= 256, one per lane) of the rows r0 .. r0 + hr - 1
 // (hr <= TY).  Step t: every lane collides its column for the rows r0 - 1 ..
@@ -309,10 +338,8 @@ __device__ __forceinline__ void step2_tile(const T* __restrict__ g, T* __restric
                                            double* __restrict__ rowpart, double* __restrict__ colpart) {
   constexpr int Q = 5;
   constexpr uint32_t S = sizeof(T);
-  constexpr int NP = 256 / TY;
   __shared__ T l1[TY][258], l2[TY][258];  // [row][1 + lane]; 0: left halo (f*_1), 257: right halo (f*_2)
-  __shared__ double red[SAMPLE ? TY : 1][SAMPLE ? 256 : 1];
-  __shared__ double red2[SAMPLE ? TY : 1][SAMPLE ? NP : 1];
+  __shared__ double redw[SAMPLE ? TY : 1][4];  // per row, the four waves' column sums
   const uint32_t nx = (uint32_t)P.nx, ny = (uint32_t)P.ny, n = (uint32_t)P.n;
   const int lane = threadIdx.x;
   const uint32_t x0 = tx * 256u, r0 = ty * (uint32_t)TY;
@@ -334,29 +361,26 @@ __device__ __forceinline__ void step2_tile(const T* __restrict__ g, T* __restric
   };
   T fs[TY + 2][Q];
   const bool own = lane < w;
-  if (own) {
-    const uint32_t x = x0 + (uint32_t)lane;
+  const uint32_t xo = x0 + (uint32_t)(own ? lane : 0);
+  double col = 0;
 #pragma unroll
-    for (int k = 0; k < TY + 2; ++k) {
-      if (k <= hr + 1) {
-        const int rr = (int)r0 - 1 + k;  // -1 .. r0 + hr
-        const uint32_t r = rr < 0 ? (uint32_t)(rr + (int)ny) : ((uint32_t)rr >= ny ? (uint32_t)rr - ny : (uint32_t)rr);
-        if constexpr (SAMPLE) {
-          double rho = 0;
-          first(x, r, fs[k], (k >= 1 && k <= hr) ? &rho : nullptr);
-          if (k >= 1 && k <= TY) red[k - 1][lane] = (k <= hr) ? rho : 0.0;
-        } else {
-          first(x, r, fs[k], nullptr);
-        }
-      } else if constexpr (SAMPLE) {
-        if (k >= 1 && k <= TY) red[k - 1][lane] = 0.0;
-      }
+  for (int k = 0; k < TY + 2; ++k) {
+    double rho = 0;
+    if (own && k <= hr + 1) {
+      const int rr = (int)r0 - 1 + k;  // -1 .. r0 + hr
+      const uint32_t r = rr < 0 ? (uint32_t)(rr + (int)ny) : ((uint32_t)rr >= ny ? (uint32_t)rr - ny : (uint32_t)rr);
+      first(xo, r, fs[k], (SAMPLE && k >= 1 && k <= hr) ? &rho : nullptr);
     }
     if constexpr (SAMPLE) {
-      double col = 0;
-      for (int k = 0; k < hr; ++k) col += red[k][lane];
-      colpart[(int64_t)ty * nx + x] = col;
+      if (k >= 1 && k <= TY) {  // owned row k - 1: column sum in row order, row sum over the lanes
+        if (k <= hr) col += rho;
+        const double v = wave_sum_fixed(rho);  // every lane (0 where none)
+        if ((lane & 63) == 0) redw[k - 1][lane >> 6] = v;
+      }
     }
+  }
+  if (own) {
+    if constexpr (SAMPLE) colpart[(int64_t)ty * nx + xo] = col;
 #pragma unroll
     for (int k = 0; k < TY; ++k) {
       if (k < hr) {
@@ -375,23 +399,10 @@ __device__ __forceinline__ void step2_tile(const T* __restrict__ g, T* __restric
       else l2[k][1 + w] = fh[2];
     }
   }
-  if constexpr (SAMPLE) {
-    if (!own)
-      for (int k = 0; k < TY; ++k) red[k][lane] = 0.0;
-  }
   __syncthreads();
-  if constexpr (SAMPLE) {  // row partials: TY consecutive columns, then the NP partials in order
-    const int rr = lane / NP, part = lane % NP;
-    double acc = 0;
-#pragma unroll
-    for (int j = 0; j < TY; ++j) acc += red[rr][part * TY + j];
-    red2[rr][part] = acc;
-    __syncthreads();
-    if (lane < TY && lane < hr) {
-      double a2 = 0;
-      for (int p2 = 0; p2 < NP; ++p2) a2 += red2[lane][p2];
-      rowpart[(int64_t)tx * ny + r0 + lane] = a2;
-    }
+  if constexpr (SAMPLE) {  // row partials: the four wave sums in order
+    if (lane < TY && lane < hr)
+      rowpart[(int64_t)tx * ny + r0 + lane] = ((redw[lane][0] + redw[lane][1]) + redw[lane][2]) + redw[lane][3];
   }
   if (!own) return;
   const uint32_t x = x0 + (uint32_t)lane;

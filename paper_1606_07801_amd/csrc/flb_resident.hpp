@@ -76,33 +76,6 @@ __host__ __device__ constexpr size_t res_lds_bytes(int64_t n, int q, int s, int6
          8 * (size_t)((lsum + 1) & ~1ll) + 16 * (size_t)lsum + 8 * (size_t)kResScratch;
 }
 
-// Sum over the 64 lanes of a wave with DPP lane moves (no LDS traffic):
-// quad swaps, half-row and row mirrors leave every lane with its 16-lane row
-// sum; the four row sums are read from lanes 0, 16, 32, 48 and added in that
-// order.  The result is uniform across the wave.
-template <int CTRL>
-__device__ __forceinline__ double res_dpp(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
-__device__ __forceinline__ double res_lane(double v, int lane) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)b, lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
-__device__ __forceinline__ double res_wave_sum(double v) {
-  v += res_dpp<0xB1>(v);   // quad_perm [1, 0, 3, 2]
-  v += res_dpp<0x4E>(v);   // quad_perm [2, 3, 0, 1]
-  v += res_dpp<0x141>(v);  // row_half_mirror
-  v += res_dpp<0x140>(v);  // row_mirror
-  return ((res_lane(v, 0) + res_lane(v, 16)) + res_lane(v, 32)) + res_lane(v, 48);
-}
-
 // Largest power of two p <= cap with items * p <= NT (at least 1).
 template <int NT>
 __device__ __forceinline__ int res_parts(int items, int cap) {
@@ -175,7 +148,7 @@ __device__ __forceinline__ void res_sample_moments(const T* st, int N, double* s
   if (wave < nwa) {
 #pragma unroll
     for (int v = 0; v < M::NV; ++v) {
-      const double r = res_wave_sum(acc[v]);
+      const double r = wave_sum_fixed(acc[v]);
       if (lane == 0) scr[wave * M::NV + v] = r;
     }
   }
@@ -286,7 +259,7 @@ __device__ __forceinline__ void res_sample_sk(const ResArgs& A, const ResLocal& 
     part += r;
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  part = res_wave_sum(part);
+  part = wave_sum_fixed(part);
   if (lane == 0) scr[wave] = part;
   __syncthreads();
   double M = 0;

@@ -518,16 +518,15 @@ __global__ void k_fill_zero(double* __restrict__ p, int64_t n) {
 // FP64 density of the pre-collision state into
 //   rowpart[tx][row] = sum over the tile's columns of rho(x, row)
 //   colpart[tr][x]   = sum over the tile's rows of rho(x, row)
-// (LDS reductions in a fixed order), the inputs of the axis marginals.
+// (fixed-order sums: down the column in row order; across the row, DPP wave
+// sums of the four waves added in order), the inputs of the axis marginals.
 template <int D, typename T, int RY>
 __global__ void __launch_bounds__(256) k_step_rows_sk(const T* __restrict__ g, T* __restrict__ h,
                                                       KParams<T> P, uint32_t step, int64_t tiles_x,
                                                       int64_t nrows, double* __restrict__ rowpart,
                                                       double* __restrict__ colpart) {
   constexpr int Q = 2 * D + 1;
-  constexpr int NP = 256 / RY;  // row partials per row in the first pass
-  __shared__ double red[RY][256];
-  __shared__ double red2[RY][NP];
+  __shared__ double redw[RY][4];  // per row, the four waves' column sums
   const int64_t tile = blockIdx.x;
   const int64_t tx = tile % tiles_x, tr = tile / tiles_x;
   const uint32_t nx = (uint32_t)P.nx;
@@ -535,17 +534,17 @@ __global__ void __launch_bounds__(256) k_step_rows_sk(const T* __restrict__ g, T
   const uint32_t x = (uint32_t)(tx * 256) + tid;
   const bool valid = x < nx;
   const int64_t row0 = tr * RY;
+  const int64_t n = P.n;
+  constexpr uint32_t S = sizeof(T);
+  const uint32_t xs = valid ? x : 0;
+  const uint32_t bx = xs * S;
+  const uint32_t bxm = (xs == 0 ? nx - 1 : xs - 1) * S, bxp = (xs == nx - 1 ? 0 : xs + 1) * S;
   double col = 0;
 #pragma unroll
-  for (int r = 0; r < RY; ++r) red[r][tid] = 0.0;
-  if (valid) {
-    const int64_t n = P.n;
-    constexpr uint32_t S = sizeof(T);
-    const uint32_t bx = x * S;
-    const uint32_t bxm = (x == 0 ? nx - 1 : x - 1) * S, bxp = (x == nx - 1 ? 0 : x + 1) * S;
-    for (int r = 0; r < RY; ++r) {
-      const int64_t row = row0 + r;
-      if (row >= nrows) break;
+  for (int r = 0; r < RY; ++r) {
+    const int64_t row = row0 + r;
+    double rho = 0;
+    if (valid && row < nrows) {
       const int64_t base = row * (int64_t)nx;
       T f[Q];
       f[0] = ld_at(g + base, bx);
@@ -571,29 +570,19 @@ __global__ void __launch_bounds__(256) k_step_rows_sk(const T* __restrict__ g, T
           f[6] = ld_at(g + 6 * n + ((int64_t)y + (int64_t)ny * zp) * nx, bx);
         }
       }
-      const double rho = density_sum(f);
-      red[r][tid] = rho;
+      rho = density_sum(f);
       col += rho;
       Collide<D, T>::run(f, P, (uint64_t)base + x, step);
 #pragma unroll
       for (int i = 0; i < Q; ++i) st_at<T, false>(h + i * n + base, bx, f[i]);
     }
-    colpart[tr * (int64_t)nx + x] = col;
+    const double v = wave_sum_fixed(rho);  // every lane (0 where none)
+    if ((tid & 63) == 0) redw[r][tid >> 6] = v;
   }
+  if (valid) colpart[tr * (int64_t)nx + x] = col;
   __syncthreads();
-  {  // first pass: thread (r, part) sums RY consecutive columns of row r
-    const int r = tid / NP, part = tid % NP;
-    double acc = 0;
-#pragma unroll
-    for (int j = 0; j < RY; ++j) acc += red[r][part * RY + j];
-    red2[r][part] = acc;
-  }
-  __syncthreads();
-  if (tid < RY && row0 + tid < nrows) {
-    double acc = 0;
-    for (int p2 = 0; p2 < NP; ++p2) acc += red2[tid][p2];
-    rowpart[tx * nrows + row0 + tid] = acc;
-  }
+  if (tid < RY && row0 + tid < nrows)
+    rowpart[tx * nrows + row0 + tid] = ((redw[tid][0] + redw[tid][1]) + redw[tid][2]) + redw[tid][3];
 }
 
 }  // namespace flb
