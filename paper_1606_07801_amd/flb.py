@@ -362,10 +362,13 @@ class Lattice:
             kp, nk = _ptr(kv), len(kv)
         out = np.zeros(max(nk, 1024), dtype=np.float64)
         check(lib.flb_structure_factor(self.handle, kp, nk, md, _ptr(out)))
+        if md == SK_RESET:
+            self._sk_nk = nk
         if md == SK_SNAPSHOT:
             return out[:nk].copy()
-        if md == SK_READ:
-            return out
+        if md == SK_READ:  # the accumulator's k-list length when this object set it
+            n = getattr(self, "_sk_nk", None)
+            return out[:n].copy() if n is not None else out
         return None
 
     def set_sampling(self, every, kvecs=None):
@@ -373,6 +376,7 @@ class Lattice:
         if every and kvecs is not None:
             kv = self._kvec(kvecs)
             check(load().flb_set_sampling(self.handle, int(every), _ptr(kv), len(kv)))
+            self._sk_nk = len(kv)
         else:
             check(load().flb_set_sampling(self.handle, 0, None, 0))
 
