@@ -198,8 +198,9 @@ def test_flat_structure_factor_gpu_low_density_local():
 
 
 @pytest.mark.parametrize("precision", [4, 8])
-@pytest.mark.parametrize("d,dims", [(1, (300,)), (2, (300, 70)), (3, (40, 33, 17))])
+@pytest.mark.parametrize("d,dims", [(1, (300,)), (1, (5000,)), (2, (300, 70)), (3, (40, 33, 17))])
 def test_sampling_while_stepping(d, dims, precision):
+    # (1, (300,)) runs in the LDS-resident kernel, the others in the HBM kernels
     # the sampled step leaves the trajectory bit-identical, and its S(k)
     # accumulation equals sampling the same states by a separate pass
     f0 = poisson_state(d, dims, 10.0, seed=12)
