@@ -112,6 +112,11 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) {
   return xcd < r ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
 }
 
+template <int D, typename T, int RY, bool NT>
+__device__ __forceinline__ void flat_tile(const T* __restrict__ g, T* __restrict__ h,
+                                          const KParams<T>& P, uint32_t step, int64_t s0,
+                                          uint32_t lane);
+
 // Flat step: block b covers sites b * 256 * RY ... (flat_tile).  Blocks keep
 // the dispatcher's round-robin XCD placement: an XCD-contiguous assignment
 // saved the halo re-fetches at tile edges (2.5 % of the reads) but measured
@@ -525,7 +530,6 @@ __global__ void k_to_canonical(const T* __restrict__ g, T* __restrict__ f, int64
 template <int D, typename T>
 __global__ void k_from_canonical(const T* __restrict__ f, T* __restrict__ g, int64_t nx, int64_t ny,
                                  int64_t nz) {
-  constexpr int Q = 2 * D + 1;
   const int64_t n = nx * ny * nz;
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
        s += (int64_t)gridDim.x * blockDim.x) {

@@ -28,7 +28,6 @@
 namespace flb {
 
 constexpr int kResThreads = 1024;
-constexpr int kResWaves = kResThreads / 64;
 constexpr int kResScratch = 2 * kResThreads;  // doubles of LDS scratch
 constexpr int kResMaxSites = 4 * kResThreads;
 constexpr int kResMaxChunk = 1 << 16;         // steps per launch
