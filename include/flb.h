@@ -312,9 +312,12 @@ typedef struct {
                            member (lanes filled across row ends), 1 = 256 x item_rows
                            row tiles */
   int32_t depth;        /* temporal blocking of D2Q5 members in HBM: 2 = two steps per
-                           pass (256 x 8 tiles with a one-site halo; a chunk of odd
+                           pass (width x 8 tiles with a one-site halo; a chunk of odd
                            length ends with one single step), 1 = one step per pass;
                            0 -> 2.  Results are bit-identical either way. */
+  int32_t width;        /* depth 2: columns per two-step tile, 64, 128 or 256 (narrower
+                           tiles leave fewer lanes idle on uneven widths, at more halo
+                           work); 0 -> 256.  Bit-identical either way. */
   void* hip_stream;     /* stream of all batch work (NULL = a stream of its own) */
 } flb_batch_opts;
 

@@ -68,14 +68,14 @@ __global__ void __launch_bounds__(256) k_batch_flat(const BatchRep<T>* __restric
 }
 
 // Two-step work list (D2Q5 members at depth 2): item w is the tile
-// item_tile[w] = ty * tiles_x + tx (256 columns x kBatchTwoTY rows) of member
+// item_tile[w] = ty * tiles_x + tx (TW columns x kBatchTwoTY rows) of member
 // item_rep[w]; steps k and k + 1 of the chunk in one pass.
 constexpr int kBatchTwoTY = 8;
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_batch_two(const BatchRep<T>* __restrict__ reps,
-                                                   const int32_t* __restrict__ item_rep,
-                                                   const int32_t* __restrict__ item_tile, int nitems, int k) {
+template <typename T, int TW>
+__global__ void __launch_bounds__(TW) k_batch_two(const BatchRep<T>* __restrict__ reps,
+                                                  const int32_t* __restrict__ item_rep,
+                                                  const int32_t* __restrict__ item_tile, int nitems, int k) {
   for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
     const int r = __builtin_amdgcn_readfirstlane(item_rep[w]);
     const uint32_t tile = __builtin_amdgcn_readfirstlane(item_tile[w]);
@@ -85,8 +85,8 @@ __global__ void __launch_bounds__(256) k_batch_two(const BatchRep<T>* __restrict
     const int par = member_parity(R, k);
     const T* g = (const T*)(R.pop + par * R.plane);
     T* h = (T*)(R.pop + (par ^ 1) * R.plane);
-    const uint32_t tx2 = (uint32_t)((P.nx + 255) / 256);
-    step2_tile<T, kBatchTwoTY, true, false>(g, h, P, step, tile % tx2, tile / tx2, nullptr, nullptr);
+    const uint32_t tx2 = (uint32_t)((P.nx + TW - 1) / TW);
+    step2_tile<T, kBatchTwoTY, true, false, TW>(g, h, P, step, tile % tx2, tile / tx2, nullptr, nullptr);
   }
 }
 
@@ -273,7 +273,8 @@ int rebuild_t(flb_batch* b) {
     const bool flat = b->o.tiling == 0 && (int64_t)h->plane < (1ll << 32);
     if (b->o.depth == 2 && h->d == 2 && (int64_t)h->plane < (1ll << 32)) {
       R.depth = 2;
-      const int64_t t2 = ((h->p.n[0] + 255) / 256) * ((h->p.n[1] + kBatchTwoTY - 1) / kBatchTwoTY);
+      const int64_t tw = b->o.width;
+      const int64_t t2 = ((h->p.n[0] + tw - 1) / tw) * ((h->p.n[1] + kBatchTwoTY - 1) / kBatchTwoTY);
       const int64_t tf = (h->n + 256 * kBatchRY - 1) / (256 * kBatchRY);
       if (t2 >= (1ll << 31) || tf >= (1ll << 31)) return fail(FLB_EINVAL, "member %d has too many tiles", i);
       for (int64_t t = 0; t < t2; ++t) {
@@ -356,7 +357,9 @@ void enqueue_chunk_t(flb_batch* b, int c) {
       if (k + 1 < c) {
         const int ni = b->nitems[7];
         const int grid = b->o.workers > 0 ? std::max(1, std::min(ni, b->o.workers)) : ni;
-        k_batch_two<T><<<grid, 256, 0, st>>>(reps, ir2, it2, ni, k);
+        if (b->o.width == 64) k_batch_two<T, 64><<<grid, 64, 0, st>>>(reps, ir2, it2, ni, k);
+        else if (b->o.width == 128) k_batch_two<T, 128><<<grid, 128, 0, st>>>(reps, ir2, it2, ni, k);
+        else k_batch_two<T, 256><<<grid, 256, 0, st>>>(reps, ir2, it2, ni, k);
       } else {
         const int ni = b->nitems[8];
         const int grid = b->o.workers > 0 ? std::max(1, std::min(ni, b->o.workers)) : ni;
@@ -440,6 +443,9 @@ int flb_batch_create(const flb_batch_opts* opts, flb_batch** out) {
     return fail(FLB_EINVAL, "item_rows must be 2, 4, 8 or 16");
   if (o.depth < 0 || o.depth > 2) return fail(FLB_EINVAL, "depth must be 0 (default), 1 or 2");
   if (o.depth == 0) o.depth = 2;
+  if (o.width != 0 && o.width != 64 && o.width != 128 && o.width != 256)
+    return fail(FLB_EINVAL, "width must be 0 (default), 64, 128 or 256");
+  if (o.width == 0) o.width = 256;
   if (o.chunk == 0) o.chunk = 16;
   flb_batch* b = new (std::nothrow) flb_batch();
   if (!b) return fail(FLB_ENOMEM, "batch allocation failed");

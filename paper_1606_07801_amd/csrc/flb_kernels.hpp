@@ -317,8 +317,10 @@ __device__ __forceinline__ double wave_sum_fixed(double v) {
   return ((lane_value(v, 0) + lane_value(v, 16)) + lane_value(v, 32)) + lane_value(v, 48);
 }
 
-// Two D2Q5 steps per pass (temporal blocking).  A workgroup owns the
-// columns x0 .. x0 + w - 1 (w <= 256, one per lane) of the rows r0 .. r0 + hr - 1
+// Two D2Q5 steps per pass (temporal blocking).  A workgroup of TW lanes
+// (TW = 256 for single lattices; 128 or 64 leave fewer lanes idle on the
+// uneven widths of an ensemble) owns the
+// columns x0 .. x0 + w - 1 (w <= TW, one per lane) of the rows r0 .. r0 + hr - 1
 // (hr <= TY).  Step t: every lane collides its column for the rows r0 - 1 ..
 // r0 + hr (the owned rows plus one halo row on each side, periodic), and a
 // few lanes of wave 0 collide the halo columns x0 - 1 and x0 + w for the
@@ -337,18 +339,21 @@ __device__ __forceinline__ double wave_sum_fixed(double v) {
 // reduction order of k_step_rows_sk for tiles of TY rows:
 //   rowpart[tx * nrows + row] = sum over the tile's columns of rho(x, row)
 //   colpart[ty * nx + x]      = sum over the tile's rows of rho(x, row)
-template <typename T, int TY, bool NT, bool SAMPLE>
+template <typename T, int TY, bool NT, bool SAMPLE, int TW = 256>
 __device__ __forceinline__ void step2_tile(const T* __restrict__ g, T* __restrict__ h, const KParams<T>& P,
                                            uint32_t step, uint32_t tx, uint32_t ty,
                                            double* __restrict__ rowpart, double* __restrict__ colpart) {
+  static_assert(TW == 64 || TW == 128 || TW == 256, "tile widths of 1, 2 or 4 waves");
+  static_assert(2 * TY <= TW, "the halo lanes are lanes 0 .. 2 TY - 1");
+  static_assert(!SAMPLE || TW == 256, "the density partials use the 256-column tiles of the sampled step");
   constexpr int Q = 5;
   constexpr uint32_t S = sizeof(T);
-  __shared__ T l1[TY][258], l2[TY][258];  // [row][1 + lane]; 0: left halo (f*_1), 257: right halo (f*_2)
+  __shared__ T l1[TY][TW + 2], l2[TY][TW + 2];  // [row][1 + lane]; 0: left halo (f*_1), TW + 1: right halo (f*_2)
   __shared__ double redw[SAMPLE ? TY : 1][4];  // per row, the four waves' column sums
   const uint32_t nx = (uint32_t)P.nx, ny = (uint32_t)P.ny, n = (uint32_t)P.n;
   const int lane = threadIdx.x;
-  const uint32_t x0 = tx * 256u, r0 = ty * (uint32_t)TY;
-  const int w = (int)(nx - x0 < 256u ? nx - x0 : 256u);
+  const uint32_t x0 = tx * (uint32_t)TW, r0 = ty * (uint32_t)TY;
+  const int w = (int)(nx - x0 < (uint32_t)TW ? nx - x0 : (uint32_t)TW);
   const int hr = (int)(ny - r0 < (uint32_t)TY ? ny - r0 : (uint32_t)TY);
   // one collision of step t at (x, r) from the storage form g; *rho receives
   // the pre-collision density when asked for

@@ -67,7 +67,7 @@ class BatchOpts(ctypes.Structure):
         ("chunk", ctypes.c_int32), ("use_graph", ctypes.c_int32),
         ("lds_max_bytes", ctypes.c_int32), ("workers", ctypes.c_int32),
         ("item_rows", ctypes.c_int32), ("tiling", ctypes.c_int32),
-        ("depth", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
+        ("depth", ctypes.c_int32), ("width", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
     ]
 
 
@@ -399,12 +399,13 @@ class Batch:
     are bit-identical to stepping each member alone."""
 
     def __init__(self, chunk=16, use_graph=True, lds_max_bytes=0, workers=0, item_rows=0, tiling=0,
-                 stream=None, depth=0):
+                 stream=None, depth=0, width=0):
         o = BatchOpts()
         o.chunk, o.use_graph, o.lds_max_bytes, o.workers = int(chunk), int(bool(use_graph)), int(lds_max_bytes), int(workers)
         o.item_rows = int(item_rows)
         o.tiling = int(tiling)
         o.depth = int(depth)
+        o.width = int(width)
         o.hip_stream = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
         h = ctypes.c_void_p()
         check(load().flb_batch_create(ctypes.byref(o), ctypes.byref(h)))

@@ -117,15 +117,15 @@ def tune(d, precision, dims, steps=100, candidates=None, write=True, verbose=Tru
     return best, results
 
 
-BATCH_DEFAULT = {"depth": 2, "tiling": 0, "chunk": 16}
+BATCH_DEFAULT = {"depth": 2, "tiling": 0, "chunk": 16, "width": 256}
 
 
 def batch_config():
     """Options of flb.Batch for ensembles: the cached batch tuning result
-    (temporal-blocking depth of the D2Q5 members, work-item tiling, graph
-    chunk), or the defaults."""
+    (temporal-blocking depth of the D2Q5 members and the width of their
+    two-step tiles, work-item tiling, graph chunk), or the defaults."""
     ent = _load().get("batch")
-    return {k: int(ent[k]) for k in BATCH_DEFAULT} if ent else dict(BATCH_DEFAULT)
+    return {k: int(ent.get(k, v)) for k, v in BATCH_DEFAULT.items()} if ent else dict(BATCH_DEFAULT)
 
 
 def pick_batch(results, within=0.01):
@@ -139,35 +139,44 @@ def pick_batch(results, within=0.01):
     return min(near, key=lambda r: (r["tiling"] != 0, r["ms"]))
 
 
-def tune_batch(make_members, steps=400, depths=(1, 2), tilings=(0, 1), chunks=(8, 16, 32), write=True,
-               verbose=True):
-    """Time the batch options on the ensemble make_members() builds (a list
-    of lattices with their state set) and cache the fastest.  Members are
-    bit-identical under every option, so only the time decides."""
-    import torch
+def _time_batch(make_members, steps, opts):
+    """ms per step of a batch of make_members() with options opts."""
     from . import flb
 
+    lats = make_members()
+    B = flb.Batch(**opts)
+    for L in lats:
+        B.admit(L)
+    B.step(2 * opts["chunk"])
+    B.sync()
+    t0 = time.perf_counter()
+    B.step(steps)
+    B.sync()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    for L in lats:
+        B.retire(L)
+        L.close()
+    B.close()
+    return ms
+
+
+def tune_batch(make_members, steps=400, depths=(1, 2), tilings=(0, 1), chunks=(8, 16, 32),
+               widths=(256, 128, 64), write=True, verbose=True):
+    """Time the batch options on the ensemble make_members() builds (a list
+    of lattices with their state set) and cache the fastest.  Members are
+    bit-identical under every option, so only the time decides.  The
+    two-step tile width only matters at depth 2."""
     results = []
     for depth in depths:
-        for tiling in tilings:
-            for chunk in chunks:
-                lats = make_members()
-                B = flb.Batch(chunk=chunk, tiling=tiling, depth=depth)
-                for L in lats:
-                    B.admit(L)
-                B.step(2 * chunk)
-                B.sync()
-                t0 = time.perf_counter()
-                B.step(steps)
-                B.sync()
-                ms = (time.perf_counter() - t0) * 1e3 / steps
-                for L in lats:
-                    B.retire(L)
-                    L.close()
-                B.close()
-                results.append(dict(depth=depth, tiling=tiling, chunk=chunk, ms=ms))
-                if verbose:
-                    print(f"[tune] batch depth={depth} tiling={tiling} chunk={chunk}: {ms * 1e3:.1f} us/step", flush=True)
+        for width in (widths if depth == 2 else (256,)):
+            for tiling in tilings:
+                for chunk in chunks:
+                    ms = _time_batch(make_members, steps, dict(chunk=chunk, tiling=tiling, depth=depth,
+                                                               width=width))
+                    results.append(dict(depth=depth, width=width, tiling=tiling, chunk=chunk, ms=ms))
+                    if verbose:
+                        print(f"[tune] batch depth={depth} width={width} tiling={tiling} chunk={chunk}: "
+                              f"{ms * 1e3:.1f} us/step", flush=True)
     best = pick_batch(results)
     if write:
         cache = _load()

@@ -46,15 +46,16 @@ def _alone(specs, precision, nsteps, t0):
 
 
 @pytest.mark.parametrize("precision", [4, 8])
-@pytest.mark.parametrize("use_graph,tiling,depth,chunk", [(True, 0, 2, 16), (False, 0, 2, 16), (True, 1, 1, 16),
-                                                          (True, 0, 1, 16), (True, 0, 2, 7)])
-def test_batch_bit_identical_to_alone(precision, use_graph, tiling, depth, chunk):
-    # depth 2: D2Q5 members in two-step passes; odd chunks and remainders end
-    # with a single step
+@pytest.mark.parametrize("use_graph,tiling,depth,chunk,width", [
+    (True, 0, 2, 16, 256), (False, 0, 2, 16, 256), (True, 1, 1, 16, 256), (True, 0, 1, 16, 256),
+    (True, 0, 2, 7, 256), (True, 0, 2, 16, 128), (True, 0, 2, 7, 64)])
+def test_batch_bit_identical_to_alone(precision, use_graph, tiling, depth, chunk, width):
+    # depth 2: D2Q5 members in two-step passes (tiles of `width` columns); odd
+    # chunks and remainders end with a single step
     specs = _specs()
     nsteps, t0 = 37, 5           # chunks of 16 (or 7) + a remainder
     ref = _alone(specs, precision, nsteps, t0)
-    B = flb.Batch(chunk=chunk, use_graph=use_graph, tiling=tiling, depth=depth)
+    B = flb.Batch(chunk=chunk, use_graph=use_graph, tiling=tiling, depth=depth, width=width)
     lats = []
     for spec in specs:
         f0, kw = _member(spec, precision)
@@ -130,6 +131,10 @@ def test_admit_retire_between_calls():
 
 
 def test_batch_errors():
+    for bad in (dict(width=96), dict(width=512), dict(depth=3)):
+        with pytest.raises(flb.FlbError) as e:
+            flb.Batch(**bad)
+        assert e.value.code == flb.FLB_EINVAL
     B = flb.Batch()
     a = flb.Lattice(1, (64,), precision=4)
     b = flb.Lattice(1, (64,), precision=8)
