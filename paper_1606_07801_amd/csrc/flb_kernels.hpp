@@ -309,12 +309,26 @@ __device__ __forceinline__ double lane_value(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-__device__ __forceinline__ double wave_sum_fixed(double v) {
+// Every lane's 16-lane row sum (the first half of wave_sum_fixed).
+__device__ __forceinline__ double row16_sum(double v) {
   v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]
   v += dpp_move<0x4E>(v);   // quad_perm [2, 3, 0, 1]
   v += dpp_move<0x141>(v);  // row_half_mirror
   v += dpp_move<0x140>(v);  // row_mirror
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum_fixed(double v) {
+  v = row16_sum(v);
   return ((lane_value(v, 0) + lane_value(v, 16)) + lane_value(v, 32)) + lane_value(v, 48);
+}
+
+// Sum of a row of 256 lanes from its sixteen 16-lane row sums p[0..15], in
+// the order of wave_sum_fixed per wave, then the four waves in order.
+__device__ __forceinline__ double sum256_from_rows16(const double* p) {
+  const double w0 = ((p[0] + p[1]) + p[2]) + p[3], w1 = ((p[4] + p[5]) + p[6]) + p[7];
+  const double w2 = ((p[8] + p[9]) + p[10]) + p[11], w3 = ((p[12] + p[13]) + p[14]) + p[15];
+  return ((w0 + w1) + w2) + w3;
 }
 
 // Two D2Q5 steps per pass (temporal blocking).  A workgroup of TW lanes
@@ -349,7 +363,7 @@ __device__ __forceinline__ void step2_tile(const T* __restrict__ g, T* __restric
   constexpr int Q = 5;
   constexpr uint32_t S = sizeof(T);
   __shared__ T l1[TY][TW + 2], l2[TY][TW + 2];  // [row][1 + lane]; 0: left halo (f*_1), TW + 1: right halo (f*_2)
-  __shared__ double redw[SAMPLE ? TY : 1][4];  // per row, the four waves' column sums
+  __shared__ double red16[SAMPLE ? TY : 1][16];  // per row, the sixteen 16-lane sums
   const uint32_t nx = (uint32_t)P.nx, ny = (uint32_t)P.ny, n = (uint32_t)P.n;
   const int lane = threadIdx.x;
   const uint32_t x0 = tx * (uint32_t)TW, r0 = ty * (uint32_t)TY;
@@ -384,8 +398,8 @@ __device__ __forceinline__ void step2_tile(const T* __restrict__ g, T* __restric
     if constexpr (SAMPLE) {
       if (k >= 1 && k <= TY) {  // owned row k - 1: column sum in row order, row sum over the lanes
         if (k <= hr) col += rho;
-        const double v = wave_sum_fixed(rho);  // every lane (0 where none)
-        if ((lane & 63) == 0) redw[k - 1][lane >> 6] = v;
+        const double v = row16_sum(rho);  // every lane (0 where none)
+        if ((lane & 15) == 0) red16[k - 1][lane >> 4] = v;
       }
     }
   }
@@ -410,9 +424,8 @@ __device__ __forceinline__ void step2_tile(const T* __restrict__ g, T* __restric
     }
   }
   __syncthreads();
-  if constexpr (SAMPLE) {  // row partials: the four wave sums in order
-    if (lane < TY && lane < hr)
-      rowpart[(int64_t)tx * ny + r0 + lane] = ((redw[lane][0] + redw[lane][1]) + redw[lane][2]) + redw[lane][3];
+  if constexpr (SAMPLE) {  // row partials: the 16-lane sums, per wave and then the waves, in order
+    if (lane < TY && lane < hr) rowpart[(int64_t)tx * ny + r0 + lane] = sum256_from_rows16(red16[lane]);
   }
   if (!own) return;
   const uint32_t x = x0 + (uint32_t)lane;

@@ -142,22 +142,52 @@ __device__ __forceinline__ void res_sample_moments(const T* st, int N, double* s
     acc[2 + Q + M::NFF] += rho > 0 ? rho : 0.0;
     acc[3 + Q + M::NFF] += rho < 0 ? 1.0 : 0.0;
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nwa = (N + 63) / 64 < NT / 64 ? (N + 63) / 64 : NT / 64;
-  if (wave < nwa) {
+  if constexpr (NT == 256) {
+    // through LDS, CV values at a time: the threads' values side by side,
+    // then 32 threads per value add 8 consecutive ones, then one thread per
+    // value adds the 32 partials (a few LDS rounds instead of a dependent
+    // chain of lane moves per value)
+    constexpr int CV = 7, PT = 32;  // CV * (256 + PT) doubles <= the scratch
+    double* part = scr + CV * NT;
 #pragma unroll
-    for (int v = 0; v < M::NV; ++v) {
-      const double r = wave_sum_fixed(acc[v]);
-      if (lane == 0) scr[wave * M::NV + v] = r;
+    for (int v0 = 0; v0 < M::NV; v0 += CV) {
+#pragma unroll
+      for (int c = 0; c < CV; ++c)
+        if (v0 + c < M::NV) scr[c * NT + threadIdx.x] = acc[v0 + c];
+      __syncthreads();
+      if (threadIdx.x < CV * PT) {
+        const int c = threadIdx.x / PT, q = threadIdx.x % PT;
+        double a = 0;
+#pragma unroll
+        for (int j = 0; j < NT / PT; ++j) a += scr[c * NT + q * (NT / PT) + j];
+        part[c * PT + q] = a;
+      }
+      __syncthreads();
+      if (threadIdx.x < CV && v0 + (int)threadIdx.x < M::NV) {
+        double r = 0;
+        for (int q = 0; q < PT; ++q) r += part[threadIdx.x * PT + q];
+        mom[M::slot(v0 + threadIdx.x)] += r;
+      }
     }
+    __syncthreads();
+  } else {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwa = (N + 63) / 64 < NT / 64 ? (N + 63) / 64 : NT / 64;
+    if (wave < nwa) {
+#pragma unroll
+      for (int v = 0; v < M::NV; ++v) {
+        const double r = wave_sum_fixed(acc[v]);
+        if (lane == 0) scr[wave * M::NV + v] = r;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < M::NV) {
+      double r = 0;
+      for (int w = 0; w < nwa; ++w) r += scr[w * M::NV + threadIdx.x];
+      mom[M::slot(threadIdx.x)] += r;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  if (threadIdx.x < M::NV) {
-    double r = 0;
-    for (int w = 0; w < nwa; ++w) r += scr[w * M::NV + threadIdx.x];
-    mom[M::slot(threadIdx.x)] += r;
-  }
-  __syncthreads();
 }
 
 // In-place radix-2 FFT of a line: X (2 L doubles, complex) receives

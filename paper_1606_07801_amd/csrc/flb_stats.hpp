@@ -518,15 +518,16 @@ __global__ void k_fill_zero(double* __restrict__ p, int64_t n) {
 // FP64 density of the pre-collision state into
 //   rowpart[tx][row] = sum over the tile's columns of rho(x, row)
 //   colpart[tr][x]   = sum over the tile's rows of rho(x, row)
-// (fixed-order sums: down the column in row order; across the row, DPP wave
-// sums of the four waves added in order), the inputs of the axis marginals.
+// (fixed-order sums: down the column in row order; across the row, DPP sums
+// of 16 lanes, added per wave and then over the waves in order), the inputs
+// of the axis marginals.
 template <int D, typename T, int RY>
 __global__ void __launch_bounds__(256) k_step_rows_sk(const T* __restrict__ g, T* __restrict__ h,
                                                       KParams<T> P, uint32_t step, int64_t tiles_x,
                                                       int64_t nrows, double* __restrict__ rowpart,
                                                       double* __restrict__ colpart) {
   constexpr int Q = 2 * D + 1;
-  __shared__ double redw[RY][4];  // per row, the four waves' column sums
+  __shared__ double red16[RY][16];  // per row, the sixteen 16-lane sums
   const int64_t tile = blockIdx.x;
   const int64_t tx = tile % tiles_x, tr = tile / tiles_x;
   const uint32_t nx = (uint32_t)P.nx;
@@ -576,13 +577,13 @@ __global__ void __launch_bounds__(256) k_step_rows_sk(const T* __restrict__ g, T
 #pragma unroll
       for (int i = 0; i < Q; ++i) st_at<T, false>(h + i * n + base, bx, f[i]);
     }
-    const double v = wave_sum_fixed(rho);  // every lane (0 where none)
-    if ((tid & 63) == 0) redw[r][tid >> 6] = v;
+    const double v = row16_sum(rho);  // every lane (0 where none)
+    if ((tid & 15) == 0) red16[r][tid >> 4] = v;
   }
   if (valid) colpart[tr * (int64_t)nx + x] = col;
   __syncthreads();
   if (tid < RY && row0 + tid < nrows)
-    rowpart[tx * nrows + row0 + tid] = ((redw[tid][0] + redw[tid][1]) + redw[tid][2]) + redw[tid][3];
+    rowpart[tx * nrows + row0 + tid] = sum256_from_rows16(red16[tid]);
 }
 
 }  // namespace flb
