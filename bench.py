@@ -165,7 +165,7 @@ def depth1_reference(torch, flb, f0, dims):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(the lattice would shard by slabs with a one-layer halo exchange per step). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(1)
