@@ -9,7 +9,11 @@ quantities the paper reports:
   <f_i f_j> - <f_i><f_j> (same expectation as the paper's estimator, whose
   large linear terms it removes);
 * ``population_moments``: <f_i> and <f_i f_j> over sites and steps (Fig. 1,
-  Table II's first two columns, Fig. 3).
+  Table II's first two columns, Fig. 3);
+* ``density_sweep``: the same as batch means over a list of mean densities,
+  with <max(rho, 0)> and the fraction of negative sites (Figs. 1 and 3);
+* ``population_distribution``: the histogram and first three moments of f_1
+  from the populations read back every step (Fig. 4, Table II).
 
     python -m paper_1606_07801_amd.experiments --table1 3 --steps 300000
 """
@@ -51,6 +55,79 @@ def dij(side, rho=120.0, steps=300_000, burn=100, omega=1.0, noise="local", law=
     rho_eq = rho
     cov = mff - np.outer(mf, mf)
     return cov / (rho_eq * np.sqrt(np.outer(w, w)))
+
+
+def density_sweep(densities, noise="local", law="uniform", omega=1.0, side=32, steps=200_000, batches=20,
+                  burn=2000, seed=3, precision=8):
+    """Fig. 1 and Fig. 3: for each mean density, batch means over `batches`
+    consecutive stretches of `steps` sampled steps of
+      f    <f_i>                 (mean over sites and steps, per population)
+      ff   <f_i f_i>             (same-site second moments, per population)
+      pos  <max(rho, 0)>         (the mean noise density of local noise)
+      neg  fraction of sites with rho < 0
+    as arrays (len(densities), batches, ...).  The lattice starts from
+    f = w rho and is run `burn` steps first."""
+    w, _ = flb.constants(2)
+    N = side * side
+    per = steps // batches
+    out = {"f": [], "ff": [], "pos": [], "neg": []}
+    dt = np.float32 if precision == 4 else np.float64
+    for rho in densities:
+        L = flb.Lattice(2, (side, side), precision=precision, omega=omega, seed=seed, noise=noise, law=law)
+        L.set_populations(np.broadcast_to((rho * w)[:, None, None], (5, side, side)).astype(dt).copy())
+        L.step(burn)
+        L.set_moment_sampling(1)
+        prev, prev_n = None, 0
+        rows = {k: [] for k in out}
+        for _ in range(batches):
+            L.step(per)
+            sums, n = L.sampled_moments()
+            cur = {"f": sums["sum_f"], "ff": np.diag(sums["sum_ff"]), "pos": sums["sum_rho_pos"],
+                   "neg": float(sums["n_negative"])}
+            cnt = float((n - prev_n) * N)
+            for k in out:
+                rows[k].append((cur[k] - (prev[k] if prev else 0)) / cnt)
+            prev, prev_n = cur, n
+        L.close()
+        for k in out:
+            out[k].append(np.array(rows[k]))
+    return w, {k: np.array(v) for k, v in out.items()}
+
+
+def population_distribution(side, rho, steps, edges, burn=300, batches=10, omega=1.0, noise="local",
+                            law="uniform", seed=5, precision=8):
+    """Table II (all three columns) and Fig. 4: the distribution of f_1 over
+    all sites, read back after each of `steps` steps.  Returns
+      m      per-batch means of f_1, f_1^2, f_1^3, shape (batches, 3)
+      hist   counts of f_1 in the bins `edges` (values outside the range are
+             counted in under / over)
+      zero   the number of samples with f_1 exactly 0
+    The lattice starts from f = w rho and is run `burn` steps first."""
+    w, _ = flb.constants(2)
+    L = flb.Lattice(2, (side, side), precision=precision, omega=omega, seed=seed, noise=noise, law=law)
+    dt = np.float32 if precision == 4 else np.float64
+    L.set_populations(np.broadcast_to((rho * w)[:, None, None], (5, side, side)).astype(dt).copy())
+    L.step(burn)
+    edges = np.asarray(edges, dtype=np.float64)
+    hist = np.zeros(len(edges) - 1, dtype=np.int64)
+    under = over = zero = 0
+    per = steps // batches
+    m = np.zeros((batches, 3))
+    for b in range(batches):
+        acc = np.zeros(3)
+        for _ in range(per):
+            L.step(1)
+            f1 = L.get_populations()[1].astype(np.float64).ravel()
+            f2 = f1 * f1
+            acc += (f1.sum(), f2.sum(), (f2 * f1).sum())
+            hist += np.histogram(f1, edges)[0]
+            under += int((f1 < edges[0]).sum())
+            over += int((f1 > edges[-1]).sum())
+            zero += int((f1 == 0).sum())
+        m[b] = acc / (per * f1.size)
+    L.close()
+    return {"w": w, "m": m, "hist": hist, "under": under, "over": over, "zero": zero,
+            "samples": batches * per * side * side}
 
 
 def front_initial(nx, ny, rho_in, rho_out, seed=0):
