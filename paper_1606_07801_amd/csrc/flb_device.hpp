@@ -80,6 +80,15 @@ __device__ __forceinline__ T word_to_uniform(uint32_t r) {
   return (T)((r >> 9) * 2u + 1u) * (T)5.9604644775390625e-08;  // 2^-24
 }
 
+// The same value in two instructions: one funnel shift places r's top 23
+// bits under the exponent field of 1.0, giving x = 1 + (r >> 9) 2^-23 in
+// [1, 2), and x - (1 - 2^-24) = (2 (r >> 9) + 1) 2^-24 is representable, so
+// the subtraction is exact.
+template <>
+__device__ __forceinline__ float word_to_uniform<float>(uint32_t r) {
+  return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, r, 9u)) - 0x1.fffffep-1f;
+}
+
 // Box-Muller pair from two Philox words: with u0, u1 their uniforms,
 // z0 = R cos(2 pi u1), z1 = R sin(2 pi u1), R = sqrt(-2 ln u0).
 //
