@@ -25,14 +25,17 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+PEAK_VALU_GINST = 256 * 2.4  # G wave64 VALU instructions/s: 256 CUs, one per CU per clock at 2.4 GHz
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step_d2q5_4096_fp32_traffic.md")
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None if the step kernels' sources changed since the counters were
-    taken or the summary has no entry for that kernel.  The summary lists
-    blocks of "kernel: <name>" followed by "traffic_bytes_per_launch: <n>"."""
+def measured_counter(kernel, key="traffic_bytes_per_launch"):
+    """A per-launch counter figure of `kernel` from the committed counter
+    summary (key "traffic_bytes_per_launch": HBM bytes; key
+    "valu_wave_insts_per_launch": VALU instructions issued, wave-level), or
+    None if the step kernels' sources changed since the counters were taken
+    or the summary has no such entry.  The summary lists blocks of
+    "kernel: <name>" followed by "<key>: <n>" lines."""
     import hashlib
     try:
         entries, cur, src = {}, None, None
@@ -44,7 +47,7 @@ def measured_traffic(kernel):
                 src = v
             elif k == "kernel":
                 cur = v
-            elif k == "traffic_bytes_per_launch" and cur:
+            elif k == key and cur:
                 entries[cur] = int(float(v))
         h = hashlib.sha256()
         for f in ("flb_device.hpp", "flb_kernels.hpp"):
@@ -55,6 +58,23 @@ def measured_traffic(kernel):
         return entries.get(kernel)
     except (OSError, ValueError):
         return None
+
+
+def measured_traffic(kernel):
+    return measured_counter(kernel, "traffic_bytes_per_launch")
+
+
+def valu_issue(kernel, us):
+    """VALU issue rate of a launch of `kernel` lasting `us`: the counted
+    wave-level VALU instructions per launch over the time, against the
+    chip's issue peak (one wave64 instruction per CU per clock: a 16-lane
+    SIMD takes four clocks per instruction and a CU has four SIMDs)."""
+    n = measured_counter(kernel, "valu_wave_insts_per_launch")
+    if not n:
+        return None
+    rate = n / (us * 1e-6) / 1e9
+    return {"wave_insts_per_launch": n, "achieved": round(rate, 1), "peak": PEAK_VALU_GINST,
+            "unit": "G wave-instructions/s", "frac": round(rate / PEAK_VALU_GINST, 4)}
 
 
 
@@ -159,7 +179,8 @@ def depth1_reference(torch, flb, f0, dims):
     nbytes = 2 * 5 * 4 * dims[0] * dims[1]
     gbs = nbytes / (us * 1e-6) / 1e9
     return {"kernel": name, "kernel_us": round(us, 2), "achieved": round(gbs, 1),
-            "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": measured_traffic(name)}
+            "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": measured_traffic(name),
+            "valu": valu_issue(name, us)}
 
 
 def main():
@@ -222,6 +243,7 @@ def main():
             "kernel": kernel_name(cfg), "kernel_us": round(kern_ms * 1e3, 2),
             "bytes_per_launch": bytes_per_launch, "steps_per_launch": spl,
             "measured_hbm_gbs": round(traffic / (kern_ms * 1e-3) / 1e9, 1) if traffic else None,
+            "valu": valu_issue(kernel_name(cfg), kern_ms * 1e3),
         },
         "step_kernel_mlups": round(spl * N / (kern_ms * 1e-3) / 1e6, 1),
         "depth1": depth1,
