@@ -1,5 +1,5 @@
 """The paper's equilibrium measurements reproduced on the GPU path, with the
-paper's own noise law (flat, Sec. IV): Table I (finite-size d_ij on 3x3),
+paper's own noise law (flat, Sec. IV): Table I (finite-size d_ij on 3x3, 10x10, 100x100),
 Table II (low-density population moments) with the histograms of Fig. 4, Fig. 1
 (the mean populations over density and relaxation time) and Fig. 3 (the
 population correlators over density, local against global noise).  The
@@ -34,6 +34,34 @@ def test_table1_3x3_dij(golden_dir):
     assert np.abs(d - closed).max() < 0.01
     assert np.abs(d - table).max() < 0.01
     assert d[0, 0] < 0.975 and np.all(d[~np.eye(5, dtype=bool)] < 0)
+
+
+@pytest.mark.parametrize("side", [10, 100])
+def test_table1_larger_lattices_dij(golden_dir, side):
+    # Table I's 10x10 and 100x100 blocks with the paper's 1.7e6 iterations.
+    # The sample covariance of N T site samples has a standard error of about
+    # sqrt((1 + d_ij^2) / (N T)) in d_ij: 1.1e-4 / 7.7e-5 (diagonal / off)
+    # at 10x10 and 1.1e-5 / 7.7e-6 at 100x100, against finite-size terms
+    # -sqrt(w_i w_j) / N of 1.7e-3 and 1.7e-5.
+    rows = _table(golden_dir, "table1_dij.txt")
+    i = rows.index(f"L {side}")
+    table = np.array([[float(x) for x in r.split()] for r in rows[i + 1:i + 6]])
+    N, T = side * side, 1_700_000
+    d = experiments.dij(side, rho=120.0, steps=T, law="uniform", noise="local", seed=13)
+    w = np.array([1 / 3] + [1 / 6] * 4)
+    closed = cf.stationary_dij(w, N)
+    se = np.sqrt((1 + closed ** 2) / (N * T))
+    z = (d - closed) / se
+    off = ~np.eye(5, dtype=bool)
+    print(f"[table1] L={side}: max |d - closed| {np.abs(d - closed).max():.2e} (max |z| {np.abs(z).max():.1f}), "
+          f"max |d - paper| {np.abs(d - table).max():.2e}; mean off-diagonal {d[off].mean():.3e} "
+          f"(closed {closed[off].mean():.3e}, paper {table[off].mean():.3e})", flush=True)
+    assert np.abs(z).max() < 6.0
+    assert np.abs(d - table).max() < 8 * se.max()
+    # the finite-size anticorrelation is resolved: the mean off-diagonal entry
+    # lies below zero by more than six of its standard errors (bounded by the
+    # largest single-entry error over sqrt(20), entries nearly independent)
+    assert d[off].mean() < -6 * se[off].max() / np.sqrt(20)
 
 
 @pytest.mark.parametrize("rho", [30.0, 1.0])
