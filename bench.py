@@ -97,11 +97,13 @@ def parse():
 
 
 def kernel_name(cfg):
-    """Name of the step kernel a launch configuration selects (as profiled)."""
+    """Name of the step kernel a launch configuration selects (as profiled)
+    for the benchmark's local Gaussian noise (the two-step kernel's instance
+    with that noise plan fixed at compile time, plan 1)."""
     nt = "true" if cfg.get("nt_store") else "false"
     if cfg.get("kernel") == "two":
         ty = cfg.get("tile_rows") or 8
-        return f"flb::k_step2_d2<float, {2 if ty <= 2 else ty}, {nt}, false>"
+        return f"flb::k_step2_d2<float, {2 if ty <= 2 else ty}, {nt}, false, 1>"
     if cfg.get("kernel") == "flat":
         return f"flb::k_step_flat<2, float, {cfg.get('tile_rows') or 2}, {nt}>"
     if cfg.get("kernel") == "plain":

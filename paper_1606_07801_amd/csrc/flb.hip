@@ -443,10 +443,14 @@ void launch_step2_t(flb_lattice* h, const T* g, T* out, uint32_t step) {
   const int ty = h->p.tile_rows ? h->p.tile_rows : 8;
   const int tiles_x = (int)((h->p.n[0] + 255) / 256);
   const bool nt = h->p.nt_store != 0;
+  // local Gaussian noise (the default) takes the instances with the noise plan fixed at compile time
+  const bool lg = h->p.noise == FLB_NOISE_LOCAL && h->p.noise_law == FLB_LAW_GAUSS;
 #define FLB_TWO(TYV)                                                                                    \
   {                                                                                                     \
     const unsigned nb = (unsigned)(tiles_x * ((h->p.n[1] + TYV - 1) / TYV));                             \
-    if (nt) k_step2_d2<T, TYV, true><<<nb, 256, 0, h->stream>>>(g, out, P, step, tiles_x);               \
+    if (lg && nt) k_step2_d2<T, TYV, true, false, kPlanLocalGauss><<<nb, 256, 0, h->stream>>>(g, out, P, step, tiles_x); \
+    else if (lg) k_step2_d2<T, TYV, false, false, kPlanLocalGauss><<<nb, 256, 0, h->stream>>>(g, out, P, step, tiles_x); \
+    else if (nt) k_step2_d2<T, TYV, true><<<nb, 256, 0, h->stream>>>(g, out, P, step, tiles_x);          \
     else k_step2_d2<T, TYV, false><<<nb, 256, 0, h->stream>>>(g, out, P, step, tiles_x);                 \
   }
   switch (ty) {
@@ -467,7 +471,12 @@ void launch_step2_sampled_t(flb_lattice* h, const T* g, T* out, uint32_t step) {
   const unsigned nb = (unsigned)(tiles_x * ((h->p.n[1] + kSampleRows - 1) / kSampleRows));
   double* rp = (double*)(h->work + h->wl.rowpart);
   double* cp = (double*)(h->work + h->wl.colbig);
-  if (h->p.nt_store)
+  const bool lg = h->p.noise == FLB_NOISE_LOCAL && h->p.noise_law == FLB_LAW_GAUSS;
+  if (lg && h->p.nt_store)
+    k_step2_d2<T, kSampleRows, true, true, kPlanLocalGauss><<<nb, 256, 0, h->stream>>>(g, out, P, step, tiles_x, rp, cp);
+  else if (lg)
+    k_step2_d2<T, kSampleRows, false, true, kPlanLocalGauss><<<nb, 256, 0, h->stream>>>(g, out, P, step, tiles_x, rp, cp);
+  else if (h->p.nt_store)
     k_step2_d2<T, kSampleRows, true, true><<<nb, 256, 0, h->stream>>>(g, out, P, step, tiles_x, rp, cp);
   else
     k_step2_d2<T, kSampleRows, false, true><<<nb, 256, 0, h->stream>>>(g, out, P, step, tiles_x, rp, cp);

@@ -32,6 +32,11 @@ namespace flb {
 
 enum NoiseMode : int { kNoiseLocal = 0, kNoiseGlobal = 1, kNoiseOff = 2 };
 enum NoiseLaw : int { kLawGauss = 0, kLawUniform = 1 };
+// Noise plan of a kernel instance: read from the parameters at run time, or
+// fixed at compile time to local noise with the Gaussian law (the default
+// configuration), which drops the run-time selections from the collision.
+// Both give the same arithmetic, so the same bits.
+enum NoisePlan : int { kPlanRuntime = 0, kPlanLocalGauss = 1 };
 
 // Everything a step kernel needs about one lattice, passed by value.
 template <typename T>
@@ -184,12 +189,12 @@ __device__ __forceinline__ void gauss_pair(uint32_t r0, uint32_t r1, double& z0,
 }
 
 // Variates for one Philox block: four unit-variance values.
-template <typename T>
+template <typename T, int NP = kPlanRuntime>
 __device__ __forceinline__ void draw4(const KParams<T>& P, uint64_t site, uint32_t step,
                                       uint32_t block, T (&z)[4]) {
   uint32_t c0 = (uint32_t)site, c1 = (uint32_t)(site >> 32), c2 = step, c3 = block;
   philox4x32_10(c0, c1, c2, c3, P.k0, P.k1);
-  if (P.law == kLawGauss) {
+  if (NP == kPlanLocalGauss || P.law == kLawGauss) {
     gauss_pair(c0, c1, z[0], z[1]);
     gauss_pair(c2, c3, z[2], z[3]);
   } else {  // flat law on (-1, 1); the sqrt(3) lives in sq_*
@@ -239,16 +244,21 @@ __device__ __forceinline__ float noise_scale(const KParams<float>& P, float rho)
   const float rn = P.noise == kNoiseLocal ? (rho > 0.0f ? rho : 0.0f) : P.rho_eq;
   return __builtin_amdgcn_sqrtf(rn);
 }
+// the same for local noise known at compile time
+__device__ __forceinline__ double noise_scale_local(double rho) { return sqrt(rho > 0.0 ? rho : 0.0); }
+__device__ __forceinline__ float noise_scale_local(float rho) {
+  return __builtin_amdgcn_sqrtf(rho > 0.0f ? rho : 0.0f);
+}
 
 // ---------------------------------------------------------------------------
 // Per-site collision.  f holds the pre-collision populations of one site in
 // the velocity order 0, +x, -x, +y, -y, +z, -z and is overwritten with the
 // post-collision populations.
-template <int D, typename T>
+template <int D, typename T, int NP = kPlanRuntime>
 struct Collide;
 
-template <typename T>
-struct Collide<1, T> {
+template <typename T, int NP>
+struct Collide<1, T, NP> {
   static constexpr int Q = 3;
   __device__ __forceinline__ static void run(T (&f)[3], const KParams<T>& P, uint64_t site,
                                              uint32_t step) {
@@ -278,13 +288,15 @@ struct Collide<1, T> {
   }
 };
 
-template <typename T>
-struct Collide<2, T> {
+template <typename T, int NP>
+struct Collide<2, T, NP> {
   static constexpr int Q = 5;
   __device__ __forceinline__ static void run(T (&f)[5], const KParams<T>& P, uint64_t site,
                                              uint32_t step) {
+    constexpr bool fixed = NP == kPlanLocalGauss;
+    const bool on = fixed || P.noise != kNoiseOff;
     T z[4];
-    if (P.noise != kNoiseOff) draw4(P, site, step, 0u, z);  // independent of f: overlaps its loads
+    if (on) draw4<T, NP>(P, site, step, 0u, z);  // independent of f: overlaps its loads
     const double rho_d = density_sum(f);
     const T rho = (T)rho_d;
     const T sx = f[1] + f[2], sy = f[3] + f[4];
@@ -293,8 +305,8 @@ struct Collide<2, T> {
     const T Mn = P.b * (sx - sy);
     const T Ms = fma(P.c1, sx + sy, -(P.c0 * f[0]));
     T x1 = 0, x2 = 0, x3 = 0, x4 = 0;
-    if (P.noise != kNoiseOff) {
-      const T sr = noise_scale(P, rho);
+    if (on) {
+      const T sr = fixed ? noise_scale_local(rho) : noise_scale(P, rho);
       const T gj = sr * P.sq_j;
       x1 = gj * z[0];
       x2 = gj * z[1];
@@ -321,8 +333,8 @@ struct Collide<2, T> {
   }
 };
 
-template <typename T>
-struct Collide<3, T> {
+template <typename T, int NP>
+struct Collide<3, T, NP> {
   static constexpr int Q = 7;
   __device__ __forceinline__ static void run(T (&f)[7], const KParams<T>& P, uint64_t site,
                                              uint32_t step) {

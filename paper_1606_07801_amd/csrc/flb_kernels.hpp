@@ -353,7 +353,7 @@ __device__ __forceinline__ double sum256_from_rows16(const double* p) {
 // reduction order of k_step_rows_sk for tiles of TY rows:
 //   rowpart[tx * nrows + row] = sum over the tile's columns of rho(x, row)
 //   colpart[ty * nx + x]      = sum over the tile's rows of rho(x, row)
-template <typename T, int TY, bool NT, bool SAMPLE, int TW = 256>
+template <typename T, int TY, bool NT, bool SAMPLE, int TW = 256, int NP = kPlanRuntime>
 __device__ __forceinline__ void step2_tile(const T* __restrict__ g, T* __restrict__ h, const KParams<T>& P,
                                            uint32_t step, uint32_t tx, uint32_t ty,
                                            double* __restrict__ rowpart, double* __restrict__ colpart) {
@@ -381,7 +381,7 @@ __device__ __forceinline__ void step2_tile(const T* __restrict__ g, T* __restric
     f[3] = ld_at(g + 3 * (int64_t)n, (rm + x) * S);
     f[4] = ld_at(g + 4 * (int64_t)n, (rp + x) * S);
     if (rho) *rho = density_sum(f);
-    Collide<2, T>::run(f, P, (uint64_t)(row + x), step);
+    Collide<2, T, NP>::run(f, P, (uint64_t)(row + x), step);
   };
   T fs[TY + 2][Q];
   const bool own = lane < w;
@@ -439,20 +439,20 @@ __device__ __forceinline__ void step2_tile(const T* __restrict__ g, T* __restric
       f[3] = fs[k][3];
       f[4] = fs[k + 2][4];
       const uint32_t s = (r0 + (uint32_t)k) * nx + x;
-      Collide<2, T>::run(f, P, (uint64_t)s, step + 1u);
+      Collide<2, T, NP>::run(f, P, (uint64_t)s, step + 1u);
 #pragma unroll
       for (int i = 0; i < Q; ++i) st_at<T, NT>(h + i * (int64_t)n, s * S, f[i]);
     }
   }
 }
 
-template <typename T, int TY, bool NT, bool SAMPLE = false>
+template <typename T, int TY, bool NT, bool SAMPLE = false, int NP = kPlanRuntime>
 __global__ void __launch_bounds__(256) k_step2_d2(const T* __restrict__ g, T* __restrict__ h,
                                                   KParams<T> P, uint32_t step, int tiles_x,
                                                   double* __restrict__ rowpart = nullptr,
                                                   double* __restrict__ colpart = nullptr) {
-  step2_tile<T, TY, NT, SAMPLE>(g, h, P, step, blockIdx.x % (uint32_t)tiles_x, blockIdx.x / (uint32_t)tiles_x,
-                                rowpart, colpart);
+  step2_tile<T, TY, NT, SAMPLE, 256, NP>(g, h, P, step, blockIdx.x % (uint32_t)tiles_x,
+                                         blockIdx.x / (uint32_t)tiles_x, rowpart, colpart);
 }
 
 // Column x of rows row0 .. row0 + RY - 1 (row0 is uniform over a wave).

@@ -17,7 +17,7 @@ def test_parse_defaults(monkeypatch):
 
 
 def test_kernel_names():
-    assert bench.kernel_name({"kernel": "two", "tile_rows": 8, "nt_store": 1}) == "flb::k_step2_d2<float, 8, true, false>"
+    assert bench.kernel_name({"kernel": "two", "tile_rows": 8, "nt_store": 1}) == "flb::k_step2_d2<float, 8, true, false, 1>"
     assert bench.kernel_name({"kernel": "flat", "tile_rows": 2, "nt_store": 1}) == "flb::k_step_flat<2, float, 2, true>"
     assert bench.steps_per_launch({"kernel": "two"}) == 2 and bench.steps_per_launch({"kernel": "flat"}) == 1
 
@@ -38,7 +38,7 @@ def test_counter_summary_reader(tmp_path, monkeypatch):
     for f in ("flb_device.hpp", "flb_kernels.hpp"):
         with open(os.path.join(ROOT, "paper_1606_07801_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    k = "flb::k_step2_d2<float, 8, true, false>"
+    k = "flb::k_step2_d2<float, 8, true, false, 1>"
     summary = tmp_path / "summary.md"
     summary.write_text(f"# t\n\n```\nkernel_source_sha256_16: {h.hexdigest()[:16]}\nkernel: {k}\n"
                        f"traffic_bytes_per_launch: 1000\nvalu_wave_insts_per_launch: 614400\n```\n")

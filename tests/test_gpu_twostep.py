@@ -15,11 +15,11 @@ pytestmark = pytest.mark.gpu
 DIMS = [(300, 70), (256, 8), (513, 33), (5, 3), (1, 7), (1000, 1), (64, 64)]
 
 
-def _run(dims, precision, kernel, steps, t0, ty=0, nt=0, sample=False):
+def _run(dims, precision, kernel, steps, t0, ty=0, nt=0, sample=False, noise="local", law="gauss"):
     dt = np.float32 if precision == 4 else np.float64
     f0 = poisson_state(2, dims, 10.0, seed=4).astype(dt)
     L = gpu_lattice(2, dims, precision, omega=1.3, omega_n=0.8, seed=99, kernel=kernel, tile_rows=ty,
-                    nt_store=nt)
+                    nt_store=nt, noise=noise, law=law)
     L.set_populations(f0, step=t0)
     out = {}
     if sample:
@@ -46,6 +46,23 @@ def test_two_step_bit_identical(dims, precision):
         got = _run(dims, precision, "two", 13, t0, ty=ty, nt=nt)
         assert got["t"] == ref["t"] == t0 + 13
         assert np.array_equal(got["f"].view(np.uint8), ref["f"].view(np.uint8)), (ty, nt)
+
+
+@pytest.mark.parametrize("precision", [4, 8])
+@pytest.mark.parametrize("noise,law", [("global", "gauss"), ("local", "uniform"), ("off", "gauss"),
+                                       ("global", "uniform")])
+def test_two_step_other_noise_plans(noise, law, precision):
+    # local Gaussian noise runs instances with the noise plan fixed at compile
+    # time; every other combination reads it from the parameters
+    dims = (300, 70)
+    ref = _run(dims, precision, "flat", 9, 5, ty=2, nt=1, noise=noise, law=law)
+    for ty, nt in ((8, 1), (4, 0)):
+        got = _run(dims, precision, "two", 9, 5, ty=ty, nt=nt, noise=noise, law=law)
+        assert np.array_equal(got["f"].view(np.uint8), ref["f"].view(np.uint8)), (ty, nt)
+    for ty in (8, 16):  # and against the fixed plan's instances: the noise changes the state
+        if noise != "local" or law != "gauss":
+            loc = _run(dims, precision, "two", 9, 5, ty=ty, nt=1)
+            assert not np.array_equal(loc["f"], ref["f"])
 
 
 def test_two_step_with_sampling():
