@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(256) k_batch_flat(const BatchRep<T>* __restric
 // item_rep[w]; steps k and k + 1 of the chunk in one pass.
 constexpr int kBatchTwoTY = 8;
 
-template <typename T, int TW>
+template <typename T, int TW, int NP = kPlanRuntime>
 __global__ void __launch_bounds__(TW) k_batch_two(const BatchRep<T>* __restrict__ reps,
                                                   const int32_t* __restrict__ item_rep,
                                                   const int32_t* __restrict__ item_tile, int nitems, int k) {
@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(TW) k_batch_two(const BatchRep<T>* __restrict_
     const T* g = (const T*)(R.pop + par * R.plane);
     T* h = (T*)(R.pop + (par ^ 1) * R.plane);
     const uint32_t tx2 = (uint32_t)((P.nx + TW - 1) / TW);
-    step2_tile<T, kBatchTwoTY, true, false, TW>(g, h, P, step, tile % tx2, tile / tx2, nullptr, nullptr);
+    step2_tile<T, kBatchTwoTY, true, false, TW, NP>(g, h, P, step, tile % tx2, tile / tx2, nullptr, nullptr);
   }
 }
 
@@ -209,6 +209,7 @@ struct flb_batch {
   size_t lds_bytes;
   int nreps;
   int sub;  // sub-tiles of kBatchRY rows per work item
+  bool two_lg;  // every depth-2 member has local Gaussian noise (compile-time noise plan)
   hipGraphExec_t exec;
   int exec_chunk;
 };
@@ -252,6 +253,7 @@ int rebuild_t(flb_batch* b) {
   std::vector<int32_t> lds;
   int64_t lmax = 0;
   const int64_t lds_max = b->o.lds_max_bytes < 0 ? -1 : (b->o.lds_max_bytes ? b->o.lds_max_bytes : 65536);
+  bool two_lg = true;
   for (int i = 0; i < n; ++i) {
     flb_lattice* h = b->members[i];
     BatchRep<T>& R = reps[i];
@@ -273,6 +275,7 @@ int rebuild_t(flb_batch* b) {
     const bool flat = b->o.tiling == 0 && (int64_t)h->plane < (1ll << 32);
     if (b->o.depth == 2 && h->d == 2 && (int64_t)h->plane < (1ll << 32)) {
       R.depth = 2;
+      two_lg = two_lg && h->p.noise == FLB_NOISE_LOCAL && h->p.noise_law == FLB_LAW_GAUSS;
       const int64_t tw = b->o.width;
       const int64_t t2 = ((h->p.n[0] + tw - 1) / tw) * ((h->p.n[1] + kBatchTwoTY - 1) / kBatchTwoTY);
       const int64_t tf = (h->n + 256 * kBatchRY - 1) / (256 * kBatchRY);
@@ -328,6 +331,7 @@ int rebuild_t(flb_batch* b) {
   b->lds_spt = spt_for(lmax);
   b->lds_bytes = (size_t)(3 * lmax * (int64_t)sizeof(T));
   b->nreps = n;
+  b->two_lg = two_lg;
   b->dirty = false;
   drop_graph(b);
   return FLB_OK;
@@ -357,9 +361,13 @@ void enqueue_chunk_t(flb_batch* b, int c) {
       if (k + 1 < c) {
         const int ni = b->nitems[7];
         const int grid = b->o.workers > 0 ? std::max(1, std::min(ni, b->o.workers)) : ni;
-        if (b->o.width == 64) k_batch_two<T, 64><<<grid, 64, 0, st>>>(reps, ir2, it2, ni, k);
-        else if (b->o.width == 128) k_batch_two<T, 128><<<grid, 128, 0, st>>>(reps, ir2, it2, ni, k);
-        else k_batch_two<T, 256><<<grid, 256, 0, st>>>(reps, ir2, it2, ni, k);
+#define FLB_BTWO(TWV)                                                                         \
+  (b->two_lg ? (void)(k_batch_two<T, TWV, kPlanLocalGauss><<<grid, TWV, 0, st>>>(reps, ir2, it2, ni, k)) \
+             : (void)(k_batch_two<T, TWV><<<grid, TWV, 0, st>>>(reps, ir2, it2, ni, k)))
+        if (b->o.width == 64) FLB_BTWO(64);
+        else if (b->o.width == 128) FLB_BTWO(128);
+        else FLB_BTWO(256);
+#undef FLB_BTWO
       } else {
         const int ni = b->nitems[8];
         const int grid = b->o.workers > 0 ? std::max(1, std::min(ni, b->o.workers)) : ni;
@@ -459,6 +467,7 @@ int flb_batch_create(const flb_batch_opts* opts, flb_batch** out) {
   b->nlds = 0;
   b->nreps = 0;
   b->sub = o.item_rows ? o.item_rows / kBatchRY : 1;
+  b->two_lg = false;
   for (int d = 0; d < 9; ++d) b->nitems[d] = 0;
   hipError_t e = hipGetDevice(&b->device);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, b->device);

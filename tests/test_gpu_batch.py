@@ -75,6 +75,44 @@ def test_batch_bit_identical_to_alone(precision, use_graph, tiling, depth, chunk
     B.close()
 
 
+@pytest.mark.parametrize("precision", [4, 8])
+@pytest.mark.parametrize("plans", [("local", "gauss"), ("global", "gauss"), ("local", "uniform"), ("off", "gauss")])
+def test_batch_noise_plans(precision, plans):
+    # D2Q5 members at depth 2: an all local-Gaussian batch runs the instances
+    # with that noise plan fixed at compile time; one member of another plan
+    # switches the batch to reading it from the parameters
+    noise, law = plans
+    members = [((128, 130), 1.3, 8.0, 3, "local", "gauss"), ((300, 17), 0.9, 20.0, 4, noise, law),
+               ((257, 64), 1.7, 2.0, 5, "local", "gauss")]
+    nsteps, t0 = 21, 3
+    dt = np.float32 if precision == 4 else np.float64
+    w = oracle.make_lattice(2).w
+
+    def make(m):
+        dims, omega, rho, seed, nz, lw = m
+        L = flb.Lattice(2, dims, precision=precision, omega=omega, seed=seed, noise=nz, law=lw)
+        L.set_populations(inputs.poisson_counts(dims, rho * w, seed=seed).astype(dt), step=t0)
+        return L
+
+    ref = []
+    for m in members:
+        L = make(m)
+        L.step(nsteps)
+        ref.append(L.get_populations())
+        L.close()
+    B = flb.Batch(chunk=8, depth=2)
+    lats = [make(m) for m in members]
+    for L in lats:
+        B.admit(L)
+    B.step(nsteps)
+    B.sync()
+    for L, r, m in zip(lats, ref, members):
+        B.retire(L)
+        assert np.array_equal(L.get_populations().view(np.uint8), r.view(np.uint8)), m
+        L.close()
+    B.close()
+
+
 def test_batch_members_match_oracle():
     specs = [s for s in _specs() if s[0] == 1 and s[1][0] <= 1000] + [s for s in _specs() if s[0] == 3]
     B = flb.Batch(chunk=8)
