@@ -82,6 +82,41 @@ def test_d2q5_4096_sine_rho10(precision, omega):
 
 
 @pytest.mark.parametrize("precision", [4, 8])
+def test_d2q5_two_step_at_its_size_limit(precision):
+    # The two-step and flat kernels address each population plane with 32-bit
+    # byte offsets and accept Q N precision < 2^32: run them on the largest
+    # ragged box under that limit (about 4.3 GB of populations) and check
+    # sampled sites, the far corners included, against the oracle.
+    d = 2
+    nx = 16387 if precision == 4 else 10243
+    ny = (2 ** 32 - 1) // (5 * precision * nx)
+    assert 5 * precision * nx * ny < 2 ** 32 <= 5 * precision * nx * (ny + 1)
+    dims = (nx, ny)
+    lat = oracle.make_lattice(d)
+    dt = np.float32 if precision == 4 else np.float64
+    x = np.arange(nx, dtype=np.int64)
+    y = np.arange(ny, dtype=np.int64)[:, None]
+    # density 10 (1 + 0.1 sin 2 pi x / nx) plus a hashed term in [0, 1) that
+    # differs from row to row, so that a wrong row or plane offset shows
+    rho = (((x * 2654435761 + y * 40503) % 1024).astype(dt) / dt(1024)
+           + (10.0 * (1.0 + 0.1 * np.sin(2.0 * np.pi * x / nx))).astype(dt))
+    f0 = np.empty((5, ny, nx), dtype=dt)
+    for i in range(5):
+        np.multiply(rho, dt(lat.w[i]), out=f0[i])
+    del rho
+    cfg = tune.best_config(d, precision, dims)
+    assert cfg["kernel"] == "two"
+    L = gpu_lattice(d, dims, precision, omega=1.0, seed=0, **cfg)
+    L.set_populations(f0)
+    p = oracle.Params(d=2, omega_j=1.0, seed=0)
+    L.step(2)        # one two-step pass
+    assert _check_at(L, f0, p, 4000, f"D2Q5 {nx}x{ny} fp{8 * precision} (limit)") <= RTOL[precision]
+    L.step(3)        # a pass and a single flat step
+    assert _check_at(L, f0, p, 4000, f"D2Q5 {nx}x{ny} fp{8 * precision} (limit)") <= RTOL[precision]
+    L.close()
+
+
+@pytest.mark.parametrize("precision", [4, 8])
 def test_d2q5_4096_low_density(precision):
     d, dims = 2, (4096, 4096)
     lat = oracle.make_lattice(d)
