@@ -55,10 +55,14 @@ def _load():
 
 def best_config(d, precision, dims):
     """Kernel keyword arguments for a lattice: the cached tuning result, or
-    the defaults."""
+    the defaults.  The two-step and flat kernels address a population plane
+    with 32-bit byte offsets and accept only Q N precision < 2^32; larger
+    lattices of a size class tuned to one of them take the defaults."""
     ent = _load().get(_key(d, precision, dims))
     if size_class(dims) == "tiny" and (not ent or ent["kernel"] == "resident"):
         return dict(kernel="auto")      # resident when the lattice fits the LDS, else rows
+    if ent and ent["kernel"] in ("two", "flat") and (2 * d + 1) * int(np.prod(dims)) * precision >= 1 << 32:
+        ent = None
     if ent:
         return dict(kernel=ent["kernel"], tile_x=ent["tile_x"], tile_rows=ent["tile_rows"],
                     nt_store=ent.get("nt_store", 0), pipeline=ent.get("pipeline", 0))

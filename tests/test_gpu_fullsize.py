@@ -116,6 +116,33 @@ def test_d2q5_two_step_at_its_size_limit(precision):
     L.close()
 
 
+def test_d2q5_planes_beyond_4_gib():
+    # Past the 32-bit limit the tuned configuration falls back to the rows
+    # kernel (64-bit row bases): a FP32 box whose every population plane
+    # exceeds 2^32 bytes (32768 x 32769 sites, 21.5 GB of populations per
+    # buffer), one step, sampled sites and far corners against the oracle.
+    d, nx, ny = 2, 32768, 32769
+    assert nx * ny * 4 > 2 ** 32
+    dims = (nx, ny)
+    lat = oracle.make_lattice(d)
+    f0 = np.empty((5, ny, nx), dtype=np.float32)
+    x = np.arange(nx, dtype=np.int64)
+    base = (10.0 * (1.0 + 0.1 * np.sin(2.0 * np.pi * x / nx))).astype(np.float32)
+    for y0 in range(0, ny, 2048):
+        y = np.arange(y0, min(y0 + 2048, ny), dtype=np.int64)[:, None]
+        rho = ((x * 2654435761 + y * 40503) % 1024).astype(np.float32) / np.float32(1024) + base
+        for i in range(5):
+            np.multiply(rho, np.float32(lat.w[i]), out=f0[i, y0:y0 + rho.shape[0]])
+    cfg = tune.best_config(d, 4, dims)
+    assert cfg["kernel"] not in ("two", "flat")
+    L = gpu_lattice(d, dims, 4, omega=1.0, seed=0, **cfg)
+    L.set_populations(f0)
+    p = oracle.Params(d=2, omega_j=1.0, seed=0)
+    L.step(1)
+    assert _check_at(L, f0, p, 2000, f"D2Q5 {nx}x{ny} fp32 (planes > 4 GiB)") <= RTOL[4]
+    L.close()
+
+
 @pytest.mark.parametrize("precision", [4, 8])
 def test_d2q5_4096_low_density(precision):
     d, dims = 2, (4096, 4096)

@@ -34,3 +34,14 @@ def test_pick_batch_prefers_whole_member_tiles_on_a_near_tie():
     # otherwise the fastest
     assert tune.pick_batch([dict(depth=1, tiling=0, chunk=8, ms=1.0), dict(depth=2, tiling=0, chunk=8, ms=0.5)])[
         "depth"] == 2
+
+
+def test_configs_beyond_the_32_bit_plane_limit_take_the_defaults():
+    # D2Q5 FP64 at 4096^2 is tuned to the two-step kernel; a box whose
+    # Q N precision reaches 2^32 cannot use it
+    small = tune.best_config(2, 8, (4096, 4096))
+    big = tune.best_config(2, 8, (10243, 10483))      # 5 * 8 * 10243 * 10483 >= 2^32
+    edge = tune.best_config(2, 8, (10243, 10482))     # just below
+    if small["kernel"] in ("two", "flat"):
+        assert big == tune.DEFAULTS[2] and edge == small
+    assert big["kernel"] not in ("two", "flat")
