@@ -603,7 +603,40 @@ def bench_served(torch, flb, inputs, tune, args):
     for frac in (0.5, 0.9):
         res, _ = run(frac * cap / mean_work)
         out[f"at_{frac}_of_capacity"] = res
+    if not args.no_cpu_baseline:
+        out["oracle_check"] = served_oracle_check(serve, reqs)
     return out
+
+
+def served_oracle_check(serve, reqs, count=3, max_work=2e7, min_rho=5.0):
+    """The `count` cheapest requests of the stream with mean density at least
+    `min_rho` (away from the clamp at zero, where FP32 and FP64 trajectories
+    may part) and at most `max_work` site-updates, served together with
+    their final states kept, against the oracle's FP64 run of the same
+    request from the same initial state."""
+    import oracle
+    pick = sorted((r for r in reqs if r.rho >= min_rho and r.sites * r.steps <= max_work),
+                  key=lambda r: r.sites * r.steps)[:count]
+    if not pick:
+        return None
+    again = [serve.Request(i, 0.0, r.d, r.dims, r.steps, r.omega, r.rho, r.seed, keep_state=True)
+             for i, r in enumerate(pick)]
+    S = serve.Server()
+    S.run(again)
+    S.close()
+    rows, worst = [], 0.0
+    for r in again:
+        lat = oracle.make_lattice(r.d)
+        f0 = np.broadcast_to((np.float32(r.rho) * lat.w.astype(np.float32)).reshape((-1,) + (1,) * r.d),
+                             (lat.Q,) + tuple(reversed(r.dims))).astype(np.float64)
+        fo = oracle.run(f0, oracle.Params(d=r.d, omega_j=r.omega, seed=r.seed), r.steps)
+        g = r.result["state"].astype(np.float64)
+        scale = np.maximum(np.abs(fo), (r.rho * lat.w).reshape((-1,) + (1,) * r.d))
+        err = float(np.max(np.abs(g - fo) / scale))
+        worst = max(worst, err)
+        rows.append({"d": r.d, "dims": list(r.dims), "steps": r.steps, "rho": round(r.rho, 3),
+                     "max_err": err})
+    return {"requests": rows, "gpu_fp32_max_err_vs_oracle": worst}
 
 
 OTHER = {"d1q3": bench_d1q3, "d3q7": bench_d3q7, "batched": bench_batched, "served": bench_served}
