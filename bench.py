@@ -2,17 +2,23 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Workload (one "step" = one pass of the hot path over the lattice): a D2Q5
-lattice of 4096 x 4096 sites, float32 populations, mean density 10 with a
-sine mode of relative amplitude 0.1, omega = 1, local Gaussian noise, seed 0;
+Headline workload (one "step" = one pass of the hot path over the lattice):
+a D2Q5 lattice of 4096 x 4096 sites, float32 populations, mean density 10
+with a sine mode of relative amplitude 0.1 plus equilibrium noise (Poisson
+counts f_i ~ Poisson(w_i rho(x))), omega = 1, local Gaussian noise, seed 0;
 every step runs the fused stream-collide kernel, and every `--sample-every`
 steps (default 10) the sampled variant of the step also accumulates the FP64
 density marginals, from which the structure factor of 1024 axis modes is
 accumulated on the device; the FP64 lattice sums are taken at the end.
-Prints one JSON line.
+
+The same line carries, each timed in this run with its oracle error:
+the one-step kernel on the same state (depth1), the plain and the tuned
+FP64 paths (the comparator), the D3Q7 512^3 FP32 lattice (c3_*) and the
+1024 + 256 replica FP32 ensemble (c4_*).  Prints one JSON line.
 """
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,58 +31,114 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
-PEAK_VALU_GINST = 256 * 2.4  # G wave64 VALU instructions/s: 256 CUs, one per CU per clock at 2.4 GHz
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step_d2q5_4096_fp32_traffic.md")
+# VALU: one wave64 instruction per CU per clock (a 16-lane SIMD takes four
+# clocks per full-rate instruction, four SIMDs per CU), 256 CUs at 2.4 GHz.
+# SQ_ACTIVE_INST_VALU counts the same four-clock units, two for a
+# transcendental, so the same peak bounds it.
+PEAK_VALU_G = 256 * 2.4
+CSRC = os.path.join(ROOT, "paper_1606_07801_amd", "csrc")
+COUNTER_FILES = [os.path.join(ROOT, "profiles", f) for f in
+                 ("step_d2q5_4096_fp32_counters.md", "step_d3q7_512_fp32_counters.md",
+                  "batch_ensemble_fp32_counters.md")]
+# |rho| below which a collision's noise amplitude sqrt(max(rho, 0)) turns the
+# rounding of rho into differences above the tolerance: an FP32 difference d
+# of rho (~1e-7 of the populations) moves the amplitude by d / (2 sqrt(rho)),
+# which reaches 1e-5 of rho_mean w_i up to rho ~ 0.02; FP64 (1e-16, 1e-12)
+# only up to ~1e-6.  Sites whose light cone of the last HORIZON steps holds
+# such a collision are reported apart.
+NEAR_ZERO = {4: 0.05, 8: 1e-3}
+HORIZON = 12       # steps of light cone searched for such collisions
 
 
-def measured_counter(kernel, key="traffic_bytes_per_launch"):
-    """A per-launch counter figure of `kernel` from the committed counter
-    summary (key "traffic_bytes_per_launch": HBM bytes; key
-    "valu_wave_insts_per_launch": VALU instructions issued, wave-level), or
-    None if the step kernels' sources changed since the counters were taken
-    or the summary has no such entry.  The summary lists blocks of
-    "kernel: <name>" followed by "<key>: <n>" lines."""
-    import hashlib
-    try:
-        entries, cur, src = {}, None, None
-        for line in open(TRAFFIC_PROFILE):
+def log(msg):
+    """Progress line on stderr (the JSON line is the only stdout output)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def source_hash():
+    """Hash of every kernel and launch source; counter summaries taken on
+    other sources are ignored."""
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hpp", ".hip")):
+            with open(os.path.join(CSRC, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counters(kernel, files=None):
+    """Per-launch counter figures of `kernel` from the committed summaries
+    whose kernel_source_sha256_16 matches the current sources: a dict of
+    traffic_bytes_per_launch (HBM bytes, calibrated), valu_wave_insts_per_launch
+    (SQ_INSTS_VALU), valu_active_per_launch (SQ_ACTIVE_INST_VALU) and
+    valu_busy (SQ_ACTIVE_INST_VALU over 256 CUs x the per-XCD active clocks),
+    whichever the summary has.  A summary lists "kernel: <name>" lines each
+    followed by "<key>: <value>" lines."""
+    cur = source_hash()
+    out = {}
+    for path in files or COUNTER_FILES:
+        try:
+            lines = open(path).read().splitlines()
+        except OSError:
+            continue
+        src, k = None, None
+        entries = {}
+        for line in lines:
             if ":" not in line or line.startswith(("#", "|", " ", "`")):
                 continue
-            k, v = (x.strip() for x in line.split(":", 1))
-            if k == "kernel_source_sha256_16":
+            key, v = (x.strip() for x in line.split(":", 1))
+            if key == "kernel_source_sha256_16":
                 src = v
-            elif k == "kernel":
-                cur = v
-            elif k == key and cur:
-                entries[cur] = int(float(v))
-        h = hashlib.sha256()
-        for f in ("flb_device.hpp", "flb_kernels.hpp"):
-            with open(os.path.join(ROOT, "paper_1606_07801_amd", "csrc", f), "rb") as fh:
-                h.update(fh.read())
-        if h.hexdigest()[:16] != src:
-            return None
-        return entries.get(kernel)
-    except (OSError, ValueError):
-        return None
+            elif key == "kernel":
+                k = v
+            elif k and k == kernel:
+                try:
+                    entries[key] = float(v)
+                except ValueError:
+                    pass
+        if src == cur and entries:
+            out.update(entries)
+    return out
 
 
 def measured_traffic(kernel):
-    return measured_counter(kernel, "traffic_bytes_per_launch")
+    v = counters(kernel).get("traffic_bytes_per_launch")
+    return int(v) if v else None
 
 
-def valu_issue(kernel, us):
-    """VALU issue rate of a launch of `kernel` lasting `us`: the counted
-    wave-level VALU instructions per launch over the time, against the
-    chip's issue peak (one wave64 instruction per CU per clock: a 16-lane
-    SIMD takes four clocks per instruction and a CU has four SIMDs)."""
-    n = measured_counter(kernel, "valu_wave_insts_per_launch")
-    if not n:
-        return None
-    rate = n / (us * 1e-6) / 1e9
-    return {"wave_insts_per_launch": n, "achieved": round(rate, 1), "peak": PEAK_VALU_GINST,
-            "unit": "G wave-instructions/s", "frac": round(rate / PEAK_VALU_GINST, 4)}
-
-
+def roofline(kernel, us, alg_bytes, steps_per_launch, sites):
+    """Roofline object of one launch of `kernel` lasting `us` (live, HIP
+    events).  alg_bytes: the bytes a launch must move, reading and writing
+    every population once (2 Q s N; a two-step pass moves its state once
+    for two steps).  The HBM fraction uses the counted bytes when a current
+    summary has them, the algorithmic bytes otherwise; the ALU fraction is
+    SQ_ACTIVE_INST_VALU per launch over the time against 614.4 G/s.  The
+    binding roofline is the larger fraction."""
+    c = counters(kernel)
+    t = us * 1e-6
+    traffic = int(c["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in c else None
+    hbm_gbs = (traffic if traffic else alg_bytes) / t / 1e9
+    hbm = {"achieved": round(hbm_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": round(hbm_gbs / PEAK_HBM_GBS, 4), "bytes": "counted" if traffic else "algorithmic"}
+    alu = None
+    if "valu_active_per_launch" in c:
+        a = c["valu_active_per_launch"] / t / 1e9
+        alu = {"achieved": round(a, 1), "peak": PEAK_VALU_G, "unit": "G VALU quad-cycles/s",
+               "frac": round(a / PEAK_VALU_G, 4)}
+        if "valu_wave_insts_per_launch" in c:
+            alu["issue_frac"] = round(c["valu_wave_insts_per_launch"] / t / 1e9 / PEAK_VALU_G, 4)
+        if "valu_busy" in c:
+            alu["busy_frac_profiled"] = c["valu_busy"]
+    bind = "alu" if alu and alu["frac"] > hbm["frac"] else "hbm"
+    main_ = alu if bind == "alu" else hbm
+    r = {"bound": bind, "achieved": main_["achieved"], "peak": main_["peak"], "unit": main_["unit"],
+         "frac": main_["frac"], "traffic": traffic, "kernel": kernel, "kernel_us": round(us, 2),
+         "bytes_per_launch": alg_bytes, "steps_per_launch": steps_per_launch, "hbm": hbm, "alu": alu}
+    flat = {"hbm_frac_measured": hbm["frac"] if traffic else None,
+            "valu_frac": alu["frac"] if alu else None,
+            "effective_gbs": round(alg_bytes * steps_per_launch / t / 1e9, 1),
+            "kernel_mlups": round(steps_per_launch * sites / t / 1e6, 1)}
+    return r, flat
 
 
 def parse():
@@ -88,38 +150,48 @@ def parse():
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-legs", action="store_true", help="skip the D3Q7 and ensemble legs")
+    ap.add_argument("--no-check", action="store_true", help="skip the oracle checks of the legs")
     ap.add_argument("--requests", type=int, default=48, help="served workload: number of requests")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--workload", default="lattice", choices=["lattice", "d1q3", "d3q7", "batched", "served"],
-                    help="lattice: the D2Q5 4096^2 line (default); the others print their own line")
+                    help="lattice: the default line; the others print their own line")
     return ap.parse_args()
 
 
-def kernel_name(cfg):
+def kernel_name(cfg, d=2, prec="float"):
     """Name of the step kernel a launch configuration selects (as profiled)
-    for the benchmark's local Gaussian noise (the two-step kernel's instance
-    with that noise plan fixed at compile time, plan 1)."""
+    for local Gaussian noise (the two-step kernels' instances with that noise
+    plan fixed at compile time, plan 1)."""
     nt = "true" if cfg.get("nt_store") else "false"
     if cfg.get("kernel") == "two":
         ty = cfg.get("tile_rows") or 8
-        return f"flb::k_step2_d2<float, {2 if ty <= 2 else ty}, {nt}, false, 1>"
+        if d == 3:
+            return f"flb::k_step2_d3<{prec}, {nt}, 1>"
+        return f"flb::k_step2_d2<{prec}, {2 if ty <= 2 else ty}, {nt}, false, 1>"
     if cfg.get("kernel") == "flat":
-        return f"flb::k_step_flat<2, float, {cfg.get('tile_rows') or 2}, {nt}>"
+        return f"flb::k_step_flat<{d}, {prec}, {cfg.get('tile_rows') or (2 if d == 2 else 1)}, {nt}>"
     if cfg.get("kernel") == "plain":
-        return "flb::k_step_plain<2, float>"
-    return f"flb::k_step_rows<2, float, {cfg.get('tile_rows') or 4}, {nt}>"
-
-
-def workload_state(flb, inputs, n, precision):
-    w, _ = flb.constants(2)
-    rho = inputs.sine_field((n, n), 10.0, 0.1)
-    return inputs.outer(w, rho).astype(np.float32 if precision == 4 else np.float64)
+        return f"flb::k_step_plain<{d}, {prec}>"
+    return f"flb::k_step_rows<{d}, {prec}, {cfg.get('tile_rows') or 4}, {nt}>"
 
 
 def steps_per_launch(cfg):
     """Steps one launch of the dominant step kernel advances."""
     return 2 if cfg.get("kernel") == "two" else 1
+
+
+def headline_state(torch, flb, n, precision, seed=0):
+    """f_i ~ Poisson(w_i rho(x)), rho = 10 (1 + 0.1 sin 2 pi x / n), drawn on
+    the device; returned as a device tensor."""
+    from paper_1606_07801_amd import inputs
+    w, _ = flb.constants(2)
+    rho = torch.from_numpy(inputs.sine_field((n, n), 10.0, 0.1)).to("cuda")
+    lam = torch.tensor(w, dtype=torch.float64, device="cuda").reshape(-1, 1, 1) * rho[None]
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    f = torch.poisson(lam, generator=g)
+    return f.to(torch.float32 if precision == 4 else torch.float64).contiguous()
 
 
 def time_steps(torch, L, steps, sample_every, per_launch=1):
@@ -158,13 +230,42 @@ def time_steps(torch, L, steps, sample_every, per_launch=1):
     t1 = time.perf_counter()
     total = sum(e0.elapsed_time(e1) for e0, e1, _ in pairs)
     launches = sum(k for _, _, k in pairs)
-    return (t1 - t0) * 1e3 / steps, total / launches
+    return (t1 - t0) * 1e3 / steps, (total / launches if launches else float("nan"))
+
+
+def _coords(dims, n, seed):
+    """n random sites plus every corner of the box (periodic wrap)."""
+    gen = np.random.default_rng(seed)
+    pts = np.stack([gen.integers(0, L, n) for L in dims], axis=1)
+    corners = np.array(np.meshgrid(*[[0, L - 1] for L in dims], indexing="ij")).reshape(len(dims), -1).T
+    return np.concatenate([corners, pts])
+
+
+def sampled_error(g, f0, d, omega, steps, rho_mean, nsample=2000, seed=7, t0=0, precision=4):
+    """Error of the GPU state g (steps after the seeded state f0 at step t0)
+    against the oracle at sampled sites, each evolved on its own window:
+    max over all sites, max over the sites whose light cone had no
+    collision with |rho| < NEAR_ZERO, and the number of such sites."""
+    import oracle
+    lat = oracle.make_lattice(d)
+    p = oracle.Params(d=d, omega_j=omega, seed=0)
+    dims = tuple(reversed(np.asarray(f0).shape[1:]))
+    coords = _coords(dims, nsample, seed)
+    ref, minrho = oracle.run_sites(f0, lat, p, t0, steps, coords, horizon=min(steps, HORIZON))
+    idx = tuple(coords[:, a] for a in reversed(range(d)))
+    got = np.asarray(g)[(slice(None),) + idx].astype(np.float64)
+    floor = rho_mean * lat.w[:, None]
+    err = np.abs(got - ref) / np.maximum(np.abs(ref), floor)
+    ok = minrho > NEAR_ZERO[precision]
+    return {"max_err": float(err.max()), "max_err_well_conditioned": float(err[:, ok].max()) if ok.any() else None,
+            "sites": int(len(coords)), "sites_near_rho0": int((~ok).sum())}
 
 
 def depth1_reference(torch, flb, f0, dims):
     """The one-step flat kernel on the same lattice (each step reads and
-    writes every population once): its duration and HBM roofline fraction,
-    the reference for the two-step pass."""
+    writes every population once): its duration and rooflines, the
+    reference for the two-step pass; and its error against the oracle after
+    4 steps of the seeded state at sampled sites."""
     cfg = {"kernel": "flat", "tile_rows": 2, "nt_store": 1}
     L = flb.Lattice(2, dims, precision=4, omega=1.0, seed=0, noise="local", **cfg)
     L.set_populations(f0)
@@ -175,14 +276,60 @@ def depth1_reference(torch, flb, f0, dims):
     L.step(100)
     e1.record(st)
     e1.synchronize()
-    L.close()
     us = e0.elapsed_time(e1) * 1e3 / 100
-    name = kernel_name(cfg)
-    nbytes = 2 * 5 * 4 * dims[0] * dims[1]
-    gbs = nbytes / (us * 1e-6) / 1e9
-    return {"kernel": name, "kernel_us": round(us, 2), "achieved": round(gbs, 1),
-            "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": measured_traffic(name),
-            "valu": valu_issue(name, us)}
+    N = dims[0] * dims[1]
+    r, flat = roofline(kernel_name(cfg), us, 2 * 5 * 4 * N, 1, N)
+    out = {"kernel": r["kernel"], "kernel_us": r["kernel_us"], "hbm": r["hbm"], "alu": r["alu"],
+           "traffic": r["traffic"], "effective_gbs": flat["effective_gbs"]}
+    return out, L
+
+
+def fp64_paths(torch, flb, tune, f64, dims, k64, check):
+    """The comparator: the plain FP64 single-lattice path, and the tuned
+    FP64 path, on the same state; each with its error against the oracle
+    (a fresh lattice in the same launch configuration, 4 steps, sampled
+    sites)."""
+    N = dims[0] * dims[1]
+    out = {}
+    for tag, cfg in (("fp64_plain", {"kernel": "plain"}), ("fp64_tuned", tune.best_config(2, 8, dims))):
+        P = flb.Lattice(2, dims, precision=8, omega=1.0, seed=0, **cfg)
+        P.set_populations(f64)
+        P.step(10)
+        spl = steps_per_launch(cfg)
+        ms, kern = time_steps(torch, P, k64, 0, spl)
+        r, flat = roofline(kernel_name(cfg, prec="double"), kern * 1e3, 2 * 5 * 8 * N, spl, N)
+        res = {"kernel": cfg, "mlups": round(N / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
+               "effective_gbs": flat["effective_gbs"], "hbm": r["hbm"], "alu": r["alu"]}
+        if check:
+            P.set_populations(f64)
+            P.step(4)
+            res["oracle"] = sampled_error(P.get_populations(), f64.cpu().numpy(), 2, 1.0, 4, 10.0, precision=8)
+        P.close()
+        out[tag] = res
+    return out
+
+
+def sk_flatness(S, kvecs, n, rho_pos, sample_times, exclude):
+    """Flatness of the accumulated S(k) (mean over the samples) against
+    <max(rho, 0)>, the stationary value for local noise (the state starts
+    in equilibrium around the sine profile): per mode z = (S/rho_pos - 1)/sd,
+    with sd the standard deviation of the mean of correlated samples of an
+    exponential variable whose autocorrelation at lag dt is lambda(k)^(2 dt)
+    (lambda = 1 - theta (2 - cos 2 pi kx/n - cos 2 pi ky/n) at unit rates)."""
+    th = 1.0 / 3.0
+    ts = np.asarray(sample_times, dtype=np.float64)
+    zs, ratio = [], []
+    for (kx, ky), s in zip(kvecs, S):
+        if (kx, ky) in exclude:
+            continue
+        lam = 1.0 - th * (2.0 - np.cos(2 * np.pi * kx / n) - np.cos(2 * np.pi * ky / n))
+        c = np.abs(lam) ** (2.0 * np.abs(ts[:, None] - ts[None, :]))
+        sd = np.sqrt(c.sum()) / len(ts)
+        ratio.append(s / rho_pos)
+        zs.append((s / rho_pos - 1.0) / sd)
+    zs = np.asarray(zs)
+    return {"modes": int(len(zs)), "samples": int(len(ts)), "mean_ratio": round(float(np.mean(ratio)), 5),
+            "mean_z2": round(float(np.mean(zs ** 2)), 3), "max_abs_z": round(float(np.abs(zs).max()), 2)}
 
 
 def main():
@@ -205,76 +352,76 @@ def main():
     N = n * n
     Q = 5
     cfg = tune.best_config(2, 4, dims)
-    f0 = workload_state(flb, inputs, n, 4)
+    f0 = headline_state(torch, flb, n, 4)
     L = flb.Lattice(2, dims, precision=4, omega=1.0, seed=0, noise="local", **cfg)
-    L.set_populations(f0)
+    # the step counter starts where the timed region begins on a sampling step
+    se = args.sample_every
+    t0 = (-args.warmup) % se if se else 0
+    L.set_populations(f0, step=t0)
     kvecs = [(k, 0) for k in range(1, 513)] + [(0, k) for k in range(1, 513)]
-    if args.sample_every:
-        L.set_sampling(args.sample_every, kvecs)
+    if se:
+        L.set_sampling(se, kvecs)
 
     # warmup, then the timed region (all hot-path rows: step + sampled stats)
+    log(f"headline: D2Q5 {n}^2 fp32 {cfg}, warmup {args.warmup}, timed {args.steps}")
     L.step(args.warmup)
     spl = steps_per_launch(cfg)
-    ms_step, kern_ms = time_steps(torch, L, args.steps, args.sample_every, spl)
+    t_start = L.t
+    ms_step, kern_ms = time_steps(torch, L, args.steps, se, spl)
     m = L.moments()
-    S = L.structure_factor(None, mode="read")[:len(kvecs)] if args.sample_every else np.zeros(1)
+    S = L.structure_factor(None, mode="read")[:len(kvecs)] if se else None
     L.close()
-    depth1 = depth1_reference(torch, flb, f0, dims)
 
     value = N / (ms_step * 1e-3) / 1e6  # MLUPS of the whole job
-    # algorithmic: every step reads and writes every population once; a
-    # launch of the two-step kernel advances two steps
-    bytes_per_launch = spl * 2 * Q * 4 * N
-    achieved = bytes_per_launch / (kern_ms * 1e-3) / 1e9
-    traffic = measured_traffic(kernel_name(cfg))
-
+    rl, flat = roofline(kernel_name(cfg), kern_ms * 1e3, 2 * Q * 4 * N, spl, N)
     out = {
         "metric": "MLUPS", "value": round(value, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"D2Q5 {n}x{n} periodic, fp32 populations, rho=10 sine mode 0.1, "
-                        f"omega=1.0, local Gaussian noise (Philox), S(k) of 1024 axis modes "
-                        f"accumulated every {args.sample_every} steps, lattice sums at the end",
-            "kernel": cfg, "sites": N,
+            "workload": f"D2Q5 {n}x{n} periodic, fp32 populations, rho=10 sine mode 0.1 plus equilibrium "
+                        f"(Poisson) noise, omega=1.0, local Gaussian noise (Philox), S(k) of 1024 axis modes "
+                        f"accumulated every {se} steps, lattice sums at the end",
+            "kernel": cfg, "sites": N, "step0": t0,
         },
-        "roofline": {
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-            "kernel": kernel_name(cfg), "kernel_us": round(kern_ms * 1e3, 2),
-            "bytes_per_launch": bytes_per_launch, "steps_per_launch": spl,
-            "measured_hbm_gbs": round(traffic / (kern_ms * 1e-3) / 1e9, 1) if traffic else None,
-            "valu": valu_issue(kernel_name(cfg), kern_ms * 1e3),
-        },
-        "step_kernel_mlups": round(spl * N / (kern_ms * 1e-3) / 1e6, 1),
-        "depth1": depth1,
+        "roofline": rl,
+        **flat,
         "mass_drift_rel": abs(m["mass"] - m["mass0"]) / m["mass0"],
-        "sk_median_over_rho": float(np.median(S) / m["rho_eq"]),
     }
+    if se:
+        times = [t - t0 for t in range(t0, t_start + args.steps) if t % se == 0]
+        out["sk_flat"] = sk_flatness(S, kvecs, n, m["sum_rho_pos"] / N, times, {(1, 0)})
+
+    log("depth-1 reference")
+    depth1, D1 = depth1_reference(torch, flb, f0, dims)
+    out["depth1"] = depth1
+    f_host = f0.cpu().numpy()
+    if not args.no_check:
+        D1.set_populations(f0)
+        D1.step(4)
+        out["depth1"]["oracle"] = sampled_error(D1.get_populations(), f_host, 2, 1.0, 4, 10.0)
+    D1.close()
 
     if not args.no_fp64:
-        # comparator: the plain FP64 single-lattice path on the same GPU
-        f64 = workload_state(flb, inputs, n, 8)
-        P = flb.Lattice(2, dims, precision=8, omega=1.0, seed=0, kernel="plain")
-        P.set_populations(f64)
-        P.step(10)
-        k64 = max(args.steps // 4, 20)
-        ms64, kern64 = time_steps(torch, P, k64, 0)
-        P.close()
-        out["fp64_plain"] = {"mlups": round(N / (ms64 * 1e-3) / 1e6, 1), "ms_per_step": round(ms64, 4),
-                             "hbm_gbs": round(2 * Q * 8 * N / (kern64 * 1e-3) / 1e9, 1)}
-        # the tuned FP64 path (same state, same steps, no sampling)
-        cfg64 = tune.best_config(2, 8, dims)
-        P = flb.Lattice(2, dims, precision=8, omega=1.0, seed=0, **cfg64)
-        P.set_populations(f64)
-        P.step(10)
-        spl64 = steps_per_launch(cfg64)
-        ms64, kern64 = time_steps(torch, P, k64, 0, spl64)
-        P.close()
-        out["fp64_tuned"] = {"kernel": cfg64, "mlups": round(N / (ms64 * 1e-3) / 1e6, 1),
-                             "ms_per_step": round(ms64, 4),
-                             "effective_gbs": round(spl64 * 2 * Q * 8 * N / (kern64 * 1e-3) / 1e9, 1)}
+        log("fp64 paths")
+        f64 = f0.to(torch.float64)
+        out.update(fp64_paths(torch, flb, tune, f64, dims, max(args.steps // 4, 20), not args.no_check))
+        del f64
+
+    if not args.no_legs:
+        log("D3Q7 512^3 leg")
+        c3 = leg_d3q7(torch, flb, tune, args, check=not args.no_check)
+        log("ensemble leg")
+        c4 = leg_ensemble(torch, flb, inputs, tune, args, check=not args.no_check)
+        out["c3_d3q7"] = c3
+        out["c4_ensemble"] = c4
+        # flat keys (survive a parsed view of the line)
+        for k in ("mlups", "ms_per_step", "effective_gbs", "hbm_frac_measured", "valu_frac"):
+            out[f"c3_{k}"] = c3.get(k)
+            out[f"c4_{k}"] = c4.get(k)
+        out["c3_err_vs_oracle"] = (c3.get("oracle") or {}).get("max_err")
+        out["c4_err_vs_oracle_rho_ge_5"] = (c4.get("oracle") or {}).get("max_err_rho_ge_5")
 
     if args.copy_probe_mib:
         nb = args.copy_probe_mib << 20
@@ -283,27 +430,31 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        ts = time.perf_counter()
         for _ in range(10):
             dst.copy_(src)
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / 10
+        dt = (time.perf_counter() - ts) / 10
         out["copy_probe"] = {"bytes_each_way": nb, "gbs_read_plus_write": round(2 * nb / dt / 1e9, 1)}
         del src, dst
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(flb, inputs, n, f0)
+        log("cpu baseline (oracle, 4 steps of the full lattice)")
+        out["cpu_baseline"] = cpu_baseline(flb, n, f_host, cfg, se, kvecs)
+        out["err_vs_oracle"] = out["cpu_baseline"]["gpu_fp32_max_err_vs_oracle"]
 
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(flb, inputs, n, f0):
+def cpu_baseline(flb, n, f_host, cfg, se, kvecs):
     """The FP64 oracle (single-threaded numpy) on a bounded sample of the
     same workload: 4 steps of the full lattice from the seeded state.  The
-    GPU path's result from the same state is compared with it, every
-    population; sites within reach of a collision with |rho| < 1e-3 (where
-    the noise amplitude sqrt(max(rho, 0)) is not Lipschitz) during those
-    steps are counted apart."""
+    GPU path in the benchmark's launch configuration and sampling (a sampled
+    two-step pass, then an unsampled one) runs the same 4 steps from the same
+    state and is compared with it, every population; sites within reach of a
+    collision with |rho| < NEAR_ZERO[4] (where the noise amplitude
+    sqrt(max(rho, 0)) magnifies the FP32 rounding) during those steps are
+    counted apart."""
     try:
         from threadpoolctl import threadpool_limits
     except ImportError:  # pragma: no cover
@@ -319,14 +470,16 @@ def cpu_baseline(flb, inputs, n, f0):
     near = []
     dt = 0.0
     with ctx:
-        ref = f0.astype(np.float64)
+        ref = f_host.astype(np.float64)
         for t in range(nsteps):
-            near.append(np.abs(ref.sum(axis=0)) < 1e-3)  # collisions of step t near rho = 0
-            t0 = time.perf_counter()
+            near.append(np.abs(ref.sum(axis=0)) < NEAR_ZERO[4])  # collisions of step t near rho = 0
+            ts = time.perf_counter()
             ref = oracle.step(ref, lat, p, t)
-            dt += time.perf_counter() - t0
-    L = flb.Lattice(2, (n, n), precision=4, omega=1.0, seed=0, noise="local")
-    L.set_populations(f0)
+            dt += time.perf_counter() - ts
+    L = flb.Lattice(2, (n, n), precision=4, omega=1.0, seed=0, noise="local", **cfg)
+    L.set_populations(f_host)
+    if se:
+        L.set_sampling(se, kvecs)
     L.step(nsteps)
     g = L.get_populations()
     L.close()
@@ -343,9 +496,177 @@ def cpu_baseline(flb, inputs, n, f0):
     flag = np.broadcast_to(site, err.shape)
     return {"value": round(nsteps * n * n / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"{nsteps} steps of the {n}x{n} D2Q5 lattice from the seeded state ({dt:.1f} s)",
+            "gpu_kernel": cfg,
             "gpu_fp32_max_err_vs_oracle": float(err.max()),
             "gpu_fp32_max_err_well_conditioned": float(err[~flag].max()),
             "n_pops_near_rho0_reach": int(flag.sum())}
+
+
+def d3q7_state(torch, flb):
+    """rho = 5 + sqrt(5) z on the device (torch generator, seed 0), f = w rho."""
+    w, _ = flb.constants(3)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    rho = 5.0 + np.sqrt(5.0) * torch.randn((512, 512, 512), generator=g, device="cuda", dtype=torch.float32)
+    wt = torch.tensor(w, dtype=torch.float32, device="cuda").reshape(-1, 1, 1, 1)
+    f0 = (wt * rho[None]).contiguous()
+    del rho
+    return f0
+
+
+def leg_d3q7(torch, flb, tune, args, check=True):
+    """D3Q7 512^3 FP32, omega = 1.2, rho = 5 + sqrt(5) z: the tuned kernel
+    timed over max(K, 100) steps after the warmup, its rooflines, and its
+    error against the oracle (the seeded state stepped 4 steps in the same
+    launch configuration, 2000 sampled sites)."""
+    dims = (512, 512, 512)
+    N = 512 ** 3
+    cfg = tune.best_config(3, 4, dims)
+    f0 = d3q7_state(torch, flb)
+    L = flb.Lattice(3, dims, precision=4, omega=1.2, seed=0, **cfg)
+    L.set_populations(f0)
+    L.step(args.warmup)
+    steps = max(args.steps, 100)
+    spl = steps_per_launch(cfg)
+    steps -= steps % spl
+    ms, kern = time_steps(torch, L, steps, 0, spl)
+    r, flat = roofline(kernel_name(cfg, d=3), kern * 1e3, 2 * 7 * 4 * N, spl, N)
+    m = L.moments()
+    out = {"workload": "D3Q7 512^3 fp32 rho=5+sqrt(5)z, omega=1.2", "kernel": cfg, "steps": steps,
+           "ms_per_step": round(ms, 4), "mlups": round(N / (ms * 1e-3) / 1e6, 1),
+           "effective_gbs": flat["effective_gbs"], "hbm_frac_measured": flat["hbm_frac_measured"],
+           "valu_frac": flat["valu_frac"], "roofline": r,
+           "mass_drift_rel": (m["mass"] - m["mass0"]) / m["mass0"]}
+    if check:
+        log("D3Q7 oracle check")
+        L.set_populations(f0)
+        L.step(4)
+        out["oracle"] = sampled_error(L.get_populations(), f0.cpu().numpy(), 3, 1.2, 4, 5.0)
+    L.close()
+    del f0
+    return out
+
+
+def ensemble_members(torch, flb, inputs, keep=()):
+    """The ensemble's lattices with seeded Poisson initial counts (on the
+    device); host copies of the initial states of the members listed in keep."""
+    g = torch.Generator(device="cuda").manual_seed(0)
+    lats, kept = [], {}
+    for i, r in enumerate(inputs.ensemble(1024, 256, seed=0)):
+        w, _ = flb.constants(r["d"])
+        L = flb.Lattice(r["d"], r["dims"], precision=4, omega=r["omega"], seed=r["seed"])
+        shape = (len(w),) + tuple(reversed(r["dims"]))
+        lam = torch.tensor(w * r["rho"], dtype=torch.float32, device="cuda").reshape((-1,) + (1,) * r["d"])
+        f = torch.poisson(lam.expand(shape).contiguous(), generator=g)
+        L.set_populations(f)
+        if i in keep:
+            kept[i] = f.cpu().numpy()
+        lats.append(L)
+    return lats, kept
+
+
+def _check_members(flb, B, lats, reps, kept, steps):
+    """Put the kept members back to their initial states, run the whole
+    batch `steps` steps, and compare each kept member with the oracle's run
+    of the same lattice: per member the max error, and the max over sites
+    whose light cone saw no collision with |rho| < NEAR_ZERO[4].  The gate
+    is the members at mean density >= 5; below a few particles per site FP32
+    and FP64 trajectories part where the amplitude sqrt(max(rho, 0))
+    magnifies rounding, and those members are reported apart."""
+    import oracle
+    for i in kept:
+        B.retire(lats[i])
+        lats[i].set_populations(kept[i], step=0)
+        B.admit(lats[i])
+    B.step(steps)
+    B.sync()
+    rows = []
+    for i, f0 in kept.items():
+        r = reps[i]
+        B.retire(lats[i])
+        g = lats[i].get_populations().astype(np.float64)
+        B.admit(lats[i])
+        lat = oracle.make_lattice(r["d"])
+        p = oracle.Params(d=r["d"], omega_j=r["omega"], seed=r["seed"])
+        ref, minrho = oracle.run_box(f0.astype(np.float64), lat, p, 0, steps, [0] * r["d"], r["dims"],
+                                     horizon=min(steps, HORIZON))
+        floor = (r["rho"] * lat.w).reshape((-1,) + (1,) * r["d"])
+        err = np.abs(g - ref) / np.maximum(np.abs(ref), floor)
+        ok = np.broadcast_to(minrho > NEAR_ZERO[4], err.shape)
+        rows.append({"d": r["d"], "dims": list(r["dims"]), "rho": round(r["rho"], 3), "max_err": float(err.max()),
+                     "max_err_well_conditioned": float(err[ok].max()) if ok.any() else None,
+                     "sites_near_rho0": int((minrho <= NEAR_ZERO[4]).sum())})
+    hi = [row["max_err"] for row in rows if row["rho"] >= 5.0]
+    lo = [row for row in rows if row["rho"] < 5.0]
+    return {"steps": steps, "members": rows, "max_err_rho_ge_5": max(hi) if hi else None,
+            "max_err_rho_lt_5_well_conditioned": max((row["max_err_well_conditioned"] or 0.0) for row in lo) if lo else None}
+
+
+def leg_ensemble(torch, flb, inputs, tune, args, check=True):
+    """1024 D1Q3 (L ~ U{64..4096}) + 256 D2Q5 (sides ~ U{128..1024}), FP32,
+    per-replica seed / omega / density, Poisson initial counts, in one batch
+    with the tuned options: max(K, 256) steps timed after max(W, 32) warmup
+    steps; whole-step HBM and VALU fractions from the counted bytes and
+    VALU cycles of every kernel of a step; and the oracle error of nine
+    members (D1Q3 in LDS, D2Q5 in two-step passes) run again from their
+    initial states inside the full batch."""
+    reps = inputs.ensemble(1024, 256, seed=0)
+
+    def smallest(d, dense, k):
+        ids = [i for i, r in enumerate(reps) if r["d"] == d and (r["rho"] >= 5.0) == dense]
+        return sorted(ids, key=lambda i: (np.prod(reps[i]["dims"]), i))[:k]
+    # the gate: three D1Q3 (LDS) and three D2Q5 (two-step passes) members at
+    # mean density >= 5, and the largest D1Q3; one low-density member of each
+    # model reported apart
+    big = max((i for i, r in enumerate(reps) if r["d"] == 1 and r["rho"] >= 5.0), key=lambda i: reps[i]["dims"][0])
+    keep = tuple(smallest(1, True, 3) + [big] + smallest(2, True, 3) + smallest(1, False, 1) +
+                 smallest(2, False, 1)) if check else ()
+    bcfg = tune.batch_config()
+    B = flb.Batch(**bcfg)
+    lats, kept = ensemble_members(torch, flb, inputs, keep)
+    log(f"ensemble of {len(lats)} lattices created")
+    sites = 0
+    for L in lats:
+        B.admit(L)
+        sites += L.nsite
+    B.step(max(args.warmup, 32))
+    B.sync()
+    steps = max(args.steps, 256)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.step(steps)
+    B.sync()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    bytes_step = sum(2 * L.Q * 4 * L.nsite for L in lats)
+    n2 = sum(L.nsite for L in lats if L.d == 2)
+    # counted bytes and VALU cycles of one step: per chunk of c steps the
+    # LDS kernel runs once, the two-step kernel c/2 times, the advance once
+    c = bcfg["chunk"]
+    per_step = {"flb::k_batch_two<float, %d, 1>" % bcfg["width"]: 0.5, "flb::k_batch_lds_d1<float, 16>": 1.0 / c,
+                "flb::k_batch_advance<float>": 1.0 / c}
+    tb = va = 0.0
+    have = True
+    for k, f in per_step.items():
+        cnt = counters(k)
+        if "traffic_bytes_per_launch" not in cnt or "valu_active_per_launch" not in cnt:
+            have = have and k == "flb::k_batch_advance<float>"
+            continue
+        tb += f * cnt["traffic_bytes_per_launch"]
+        va += f * cnt["valu_active_per_launch"]
+    t = ms * 1e-3
+    out = {"workload": "1024 D1Q3 L~U[64,4096] + 256 D2Q5 sides~U[128,1024], fp32, per-replica seed/omega/rho",
+           "batch_options": bcfg, "replicas": len(lats), "sites": sites, "sites_d2q5": n2, "steps": steps,
+           "ms_per_step": round(ms, 4), "mlups": round(sites / t / 1e6, 1),
+           "effective_gbs": round(bytes_step / t / 1e9, 1),
+           "hbm_frac_measured": round(tb / t / 1e9 / PEAK_HBM_GBS, 4) if have else None,
+           "valu_frac": round(va / t / 1e9 / PEAK_VALU_G, 4) if have else None}
+    if check:
+        log("ensemble oracle check")
+        out["oracle"] = _check_members(flb, B, lats, reps, kept, 2 * c + 1)
+    for L in lats:
+        B.retire(L)
+        L.close()
+    B.close()
+    return out
 
 
 def _timed(torch, fn, steps):
@@ -391,6 +712,7 @@ def bench_d1q3(torch, flb, inputs, tune, args):
 
 
 def _scaled_err(g, ref, rho, w):
+    """max |g - ref| / max(|ref|, rho_mean w_i): the tests' tolerance scale."""
     d = ref.ndim - 1
     floor = rho * np.asarray(w).reshape((-1,) + (1,) * d)
     return float((np.abs(np.asarray(g, dtype=np.float64) - ref) / np.maximum(np.abs(ref), floor)).max())
@@ -427,39 +749,20 @@ def _d1q3_launch_per_step(torch, flb, f0, ks):
 
 
 def bench_d3q7(torch, flb, inputs, tune, args):
-    """D3Q7, FP32 populations, 512^3, rho = 5 + sqrt(5) z, omega = 1.2, 500 steps."""
-    dims = (512, 512, 512)
-    N = 512 ** 3
-    w, _ = flb.constants(3)
-    cfg = tune.best_config(3, 4, dims)
-    L = flb.Lattice(3, dims, precision=4, omega=1.2, seed=0, **cfg)
-    g = torch.Generator(device="cuda").manual_seed(0)
-    rho = 5.0 + np.sqrt(5.0) * torch.randn((512, 512, 512), generator=g, device="cuda", dtype=torch.float32)
-    wt = torch.tensor(w, dtype=torch.float32, device="cuda").reshape(-1, 1, 1, 1)
-    L.set_populations((wt * rho[None]).contiguous())
-    del rho
-    L.step(20)
-    steps = 500
-    ms = _timed(torch, L.step, steps)
-    m = L.moments()
-    L.close()
-    gbs = 2 * 7 * 4 * N / (ms * 1e-3) / 1e9
-    out = {"workload": "D3Q7 512^3 fp32 rho=5+sqrt(5)z, omega=1.2, 500 steps", "kernel": cfg,
-           "ms_per_step": round(ms, 4), "mlups": round(N / (ms * 1e-3) / 1e6, 1),
-           "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4),
-           "mass_drift_rel": (m["mass"] - m["mass0"]) / m["mass0"]}
+    """D3Q7, FP32 populations, 512^3, rho = 5 + sqrt(5) z, omega = 1.2, 500
+    steps (the leg of the default line with 500 timed steps), plus the
+    oracle's rate on one full step of a 512 x 512 x 128 slab."""
+    args.steps = 500
+    out = leg_d3q7(torch, flb, tune, args, check=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_d3q7(flb, inputs, cfg)
+        out["cpu_baseline"] = cpu_baseline_d3q7(inputs)
     return out
 
 
-def cpu_baseline_d3q7(flb, inputs, cfg, nsample=2000):
-    """The oracle on a bounded sample of the D3Q7 workload, on one core: its
-    rate from one full step of a 512 x 512 x 128 periodic slab of the same
-    kind of seeded Gaussian state (the per-site work of the 512^3 step); its
-    error against the GPU from one step of `nsample` sites of the seeded
-    512^3 state (each site on its own 3 x 3 x 3 window), compared with the
-    GPU's step of the whole lattice in the benchmark's launch configuration."""
+def cpu_baseline_d3q7(inputs):
+    """The oracle's rate on one core: one full step of a 512 x 512 x 128
+    periodic slab of the same kind of seeded Gaussian state (the per-site
+    work of the 512^3 step)."""
     import contextlib
 
     import oracle
@@ -475,66 +778,18 @@ def cpu_baseline_d3q7(flb, inputs, cfg, nsample=2000):
         t0 = time.perf_counter()
         oracle.step(fs, lat, p, 0)
         dt = time.perf_counter() - t0
-    del fs
-    dims = (512, 512, 512)
-    rho = inputs.gaussian_field(dims, 5.0, np.sqrt(5.0), seed=0)
-    f0 = inputs.outer(lat.w, rho).astype(np.float32)
-    del rho
-    coords = inputs.rng(1).integers(0, 512, size=(nsample, 3))
-    ref = oracle.run_sites(f0, lat, p, 0, 1, coords)
-    L = flb.Lattice(3, dims, precision=4, omega=1.2, seed=0, **cfg)
-    L.set_populations(f0)
-    L.step(1)
-    g = L.get_populations()
-    L.close()
-    got = g[:, coords[:, 2], coords[:, 1], coords[:, 0]].astype(np.float64)
-    floor = 5.0 * lat.w[:, None]
-    err = float((np.abs(got - ref) / np.maximum(np.abs(ref), floor)).max())
     n = slab[0] * slab[1] * slab[2]
     return {"value": round(n / dt / 1e6, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"one step of a 512x512x128 periodic slab ({dt:.1f} s); error at {nsample} sampled "
-                      f"sites of one step of the 512^3 lattice",
-            "gpu_fp32_max_err_vs_oracle": err}
-
-
-def ensemble_members(torch, flb, inputs):
-    """The ensemble's lattices with seeded Poisson initial counts (on the device)."""
-    g = torch.Generator(device="cuda").manual_seed(0)
-    lats = []
-    for r in inputs.ensemble(1024, 256, seed=0):
-        w, _ = flb.constants(r["d"])
-        L = flb.Lattice(r["d"], r["dims"], precision=4, omega=r["omega"], seed=r["seed"])
-        shape = (len(w),) + tuple(reversed(r["dims"]))
-        lam = torch.tensor(w * r["rho"], dtype=torch.float32, device="cuda").reshape((-1,) + (1,) * r["d"])
-        L.set_populations(torch.poisson(lam.expand(shape).contiguous(), generator=g))
-        lats.append(L)
-    return lats
+            "sample": f"one step of a 512x512x128 periodic slab ({dt:.1f} s)"}
 
 
 def bench_batched(torch, flb, inputs, tune, args):
-    """1024 D1Q3 (L ~ U{64..4096}) + 256 D2Q5 (sides ~ U{128..1024}), FP32,
-    per-replica seed / omega / density, Poisson initial counts, 2000 steps."""
-    bcfg = tune.batch_config()
-    B = flb.Batch(**bcfg)
-    lats = ensemble_members(torch, flb, inputs)
-    sites = 0
-    for L in lats:
-        B.admit(L)
-        sites += L.nsite
-    B.step(32)
-    steps = 2000
-    ms = _timed(torch, lambda n: (B.step(n), B.sync()), steps)
-    bytes_step = sum(2 * L.Q * 4 * L.nsite for L in lats)
-    for L in lats:
-        B.retire(L)
-        L.close()
-    B.close()
-    out = {"workload": "batched: 1024 D1Q3 L~U[64,4096] + 256 D2Q5 sides~U[128,1024], fp32, 2000 steps",
-           "batch_options": bcfg, "replicas": len(lats), "sites": sites, "ms_per_step": round(ms, 4),
-           "mlups": round(sites / (ms * 1e-3) / 1e6, 1),
-           "effective_gbs": round(bytes_step / (ms * 1e-3) / 1e9, 1)}
+    """The ensemble leg of the default line with 2000 timed steps, plus the
+    oracle's rate on a sample of the ensemble."""
+    args.steps = 2000
+    out = leg_ensemble(torch, flb, inputs, tune, args, check=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_batched(flb, inputs, bcfg)
+        out["cpu_baseline"] = cpu_baseline_batched(flb, inputs, tune.batch_config())
     return out
 
 
@@ -542,12 +797,17 @@ def cpu_baseline_batched(flb, inputs, bcfg, steps=100):
     """The oracle on a bounded sample of the ensemble: the first two D1Q3 and
     the first two D2Q5 replicas (seeded Poisson counts), `steps` steps each,
     timed on one core; the same replicas run as a batch with the benchmark's
-    options, compared population by population."""
+    options, compared population by population (the tests' scale:
+    max(|f|, rho_mean w_i)).  Below a few particles per site FP32 rounding
+    reaches the noise amplitude sqrt(max(rho, 0)) as sqrt(rounding), so FP32
+    and FP64 trajectories of such replicas part over many steps; the error
+    of the replicas at mean density >= 5 is reported apart, and the same
+    replicas are also run as an FP64 batch."""
     import oracle
     reps = inputs.ensemble(1024, 256, seed=0)
     pick = [r for r in reps if r["d"] == 1][:2] + [r for r in reps if r["d"] == 2][:2]
     B = flb.Batch(**bcfg)
-    runs, dt, work, err = [], 0.0, 0, 0.0
+    runs, dt, work = [], 0.0, 0
     for r in pick:
         lat = oracle.make_lattice(r["d"])
         f0 = inputs.poisson_counts(r["dims"], r["rho"] * lat.w, seed=r["seed"]).astype(np.float32)
@@ -567,15 +827,9 @@ def cpu_baseline_batched(flb, inputs, bcfg, steps=100):
         dt += time.perf_counter() - t0
         refs.append(ref)
         work += int(np.prod(r["dims"])) * steps
-        e = _scaled_err(g, ref, max(r["rho"], 1.0), lat.w)
-        err = max(err, e)
-        # below a few particles per site FP32 rounding reaches the noise
-        # amplitude sqrt(max(rho, 0)) as sqrt(rounding), so the trajectories
-        # separate over many steps; the error is reported with the density
-        per.append({"d": r["d"], "dims": list(r["dims"]), "rho": round(r["rho"], 3), "max_err": e})
+        per.append({"d": r["d"], "dims": list(r["dims"]), "rho": round(r["rho"], 3),
+                    "max_err": _scaled_err(g, ref, r["rho"], lat.w)})
     B.close()
-    # the same replicas with FP64 populations in a batch of their own: no
-    # such separation, so the whole trajectory matches the oracle
     B = flb.Batch(**bcfg)
     lats = []
     for r, lat, f0, _ in runs:
@@ -585,17 +839,17 @@ def cpu_baseline_batched(flb, inputs, bcfg, steps=100):
         lats.append(L)
     B.step(steps)
     B.sync()
-    err64 = 0.0
     for (r, lat, _, _), L, ref, row in zip(runs, lats, refs, per):
         B.retire(L)
-        e = _scaled_err(L.get_populations(), ref, max(r["rho"], 1.0), lat.w)
+        row["max_err_fp64"] = _scaled_err(L.get_populations(), ref, r["rho"], lat.w)
         L.close()
-        row["max_err_fp64"] = e
-        err64 = max(err64, e)
     B.close()
+    hi = [row["max_err"] for row in per if row["rho"] >= 5.0]
     return {"value": round(work / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"2 D1Q3 + 2 D2Q5 replicas x {steps} steps ({dt:.1f} s)",
-            "gpu_fp32_max_err_vs_oracle": err, "gpu_fp64_max_err_vs_oracle": err64, "per_replica": per}
+            "gpu_fp32_max_err_rho_ge_5": max(hi) if hi else None,
+            "gpu_fp32_max_err_all": max(row["max_err"] for row in per),
+            "gpu_fp64_max_err_all": max(row["max_err_fp64"] for row in per), "per_replica": per}
 
 
 def bench_served(torch, flb, inputs, tune, args):
@@ -651,8 +905,7 @@ def served_oracle_check(serve, reqs, count=3, max_work=2e7, min_rho=5.0):
                              (lat.Q,) + tuple(reversed(r.dims))).astype(np.float64)
         fo = oracle.run(f0, oracle.Params(d=r.d, omega_j=r.omega, seed=r.seed), r.steps)
         g = r.result["state"].astype(np.float64)
-        scale = np.maximum(np.abs(fo), (r.rho * lat.w).reshape((-1,) + (1,) * r.d))
-        err = float(np.max(np.abs(g - fo) / scale))
+        err = _scaled_err(g, fo, r.rho, lat.w)
         worst = max(worst, err)
         rows.append({"d": r.d, "dims": list(r.dims), "steps": r.steps, "rho": round(r.rho, 3),
                      "max_err": err})

@@ -296,11 +296,15 @@ int flb_gauss_map(int32_t precision, const void* d_words, int64_t n, void* d_z, 
 /* ---- batched ensembles (one launch advances many lattices) ---------------
  * A batch holds references to lattices created with flb_create (all float32
  * or all float64, all on one device).  flb_batch_step advances every member
- * by nsteps with results bit-identical to flb_step on each member alone: a
- * persistent work-list kernel covers the lattices that live in global memory,
- * and small D1Q3 lattices run whole chunks of steps inside one workgroup's
- * LDS.  Chunks of `chunk` steps are captured once into a HIP graph and
- * replayed.  Members may be admitted and retired between calls. */
+ * by nsteps with results bit-identical to flb_step on each member alone.
+ * The lattices that live in global memory are advanced by work-list
+ * launches (one workgroup per work item by default: a tile of one member,
+ * one launch per step, or per two steps for D2Q5 members at depth 2; with
+ * `workers` > 0 a persistent grid strides over the items), and small D1Q3
+ * lattices run whole chunks of steps inside one workgroup's LDS, in a launch
+ * of their own on the same stream.  Chunks of `chunk` steps are captured
+ * once into a HIP graph and replayed.  Members may be admitted and retired
+ * between calls. */
 typedef struct {
   int32_t chunk;        /* steps per graph (>= 1); 0 -> 16 */
   int32_t use_graph;    /* 1 = capture chunks in a HIP graph, 0 = eager launches */
@@ -322,7 +326,11 @@ typedef struct {
 } flb_batch_opts;
 
 int flb_batch_create(const flb_batch_opts* opts, flb_batch** out);
-/* Add a lattice; it must not be stepped on its own while it is a member. */
+/* Add a lattice; it must not be stepped on its own while it is a member.
+ * FLB_ESTATE if it is in a batch already or samples statistics while
+ * stepping (a batch step takes none: stop flb_set_sampling,
+ * flb_set_moment_sampling and flb_set_correlation first); FLB_EINVAL for a
+ * lattice with regions, of another precision or on another device. */
 int flb_batch_admit(flb_batch* b, flb_lattice* h);
 /* Remove a lattice (its state stays valid and can be read or stepped alone). */
 int flb_batch_retire(flb_batch* b, flb_lattice* h);

@@ -34,7 +34,7 @@ an independent pin say "parity unpinned".
 
 from .lattice import Lattice, make_lattice  # noqa: F401
 from .philox import philox4x32_10, words_to_uniform, box_muller  # noqa: F401
-from .step import (Params, collide, stream, step, run, noise_draws, step_sites, run_sites,  # noqa: F401
+from .step import (Params, collide, stream, step, run, noise_draws, step_sites, run_sites, run_box,  # noqa: F401
                    step_regions, run_regions)
 from .stats import (lattice_sums, structure_factor, density, population_amplitudes, correlate,  # noqa: F401
                     profile)

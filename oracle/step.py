@@ -257,6 +257,73 @@ def run_sites(f0, lat, p, t0, nsteps, coords, rho_eq=None, horizon=0):
     return W[centre]
 
 
+def run_box(f0, lat, p, t0, nsteps, origin, extent, rho_eq=None, horizon=0):
+    """Populations f_i(x, t0 + nsteps) on a box of sites, evolved from the
+    full initial state f0 at step t0.
+
+    The box holds the sites origin[a] + j, 0 <= j < extent[a], along every
+    axis a (x first; periodic coordinates).  As in run_sites, the value at x
+    after T steps depends only on the sites within distance T of x, so the
+    box is evolved on a window grown by T sites on every side, with the true
+    site indices for the noise.  After each step the window loses its
+    outermost layer: streaming inside the window is non-periodic, and only
+    that layer received values from outside it.  Returns (Q, *box shape in
+    array order, x last).
+
+    horizon > 0 also returns, per box site, the smallest |rho| of any
+    collision of the last `horizon` steps inside the site's light cone (a
+    collision at step t within L1 distance t0 + T - t of it), the sites whose
+    recent history passed near rho = 0.
+
+    Parity: pinned to step() (and the light-cone minimum to a brute-force
+    evaluation over full-lattice trajectories) on lattices small enough for
+    both, boxes wrapping around the periodic edges."""
+    Q, d = lat.Q, lat.d
+    dims = _dims(f0)
+    L = dims[::-1]
+    T = int(nsteps)
+    origin = [int(o) for o in origin]
+    extent = [int(e) for e in extent]
+    # window coordinates per axis (x first), periodic
+    wc = [(origin[a] - T + np.arange(extent[a] + 2 * T)) % L[a] for a in range(d)]
+    W = np.asarray(f0)[(slice(None),) + np.ix_(*[wc[a] for a in reversed(range(d))])].astype(np.float64)
+    gidx = np.zeros((1,) * d, dtype=np.int64)
+    for a in reversed(range(d)):
+        view = [1] * d
+        view[d - 1 - a] = wc[a].size
+        gidx = gidx * L[a] + wc[a].reshape(view)
+    if p.noise == "global" and rho_eq is None:
+        rho_eq = mean_density(np.asarray(f0))
+    inner = (slice(1, -1),) * d
+    A = None
+    for t in range(t0, t0 + T):
+        shape = W.shape[1:]
+        if horizon and t >= t0 + T - horizon:
+            a = np.abs(W.sum(axis=0))
+            A = a if A is None else np.minimum(A, a)
+            # widen by one site (L1 neighbours); outside the window counts as inf
+            grown = A.copy()
+            for ax in range(d):
+                lo = [slice(None)] * d
+                hi = [slice(None)] * d
+                lo[ax], hi[ax] = slice(0, -1), slice(1, None)
+                grown[tuple(lo)] = np.minimum(grown[tuple(lo)], A[tuple(hi)])
+                grown[tuple(hi)] = np.minimum(grown[tuple(hi)], A[tuple(lo)])
+            A = grown
+        sites = np.broadcast_to(gidx, shape).ravel().astype(np.uint64)
+        fs = collide(W.reshape(Q, -1), sites, lat, p, t, rho_eq).reshape((Q,) + shape)
+        for i in range(Q):
+            sh = tuple(int(lat.v[i, ax]) for ax in range(d))
+            W[i] = np.roll(fs[i], sh, axis=tuple(-1 - ax for ax in range(d)))
+        W = W[(slice(None),) + inner]
+        gidx = np.broadcast_to(gidx, shape)[inner]
+        if A is not None:
+            A = A[inner]
+    if horizon:
+        return W, (A if A is not None else np.full(W.shape[1:], np.inf))
+    return W
+
+
 def step_regions(f, plist, region, t, rho_eq=None):
     """One step of a lattice whose temperature and rates vary in space (Sec. IV,
     non-homogeneous systems): the sites with region[x] == r collide with the

@@ -496,6 +496,10 @@ int flb_batch_admit(flb_batch* b, flb_lattice* h) {
   if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is already in a batch");
   if (h->device != b->device) return fail(FLB_EINVAL, "lattice and batch are on different devices");
   if (h->reg_n > 0) return fail(FLB_EINVAL, "a lattice with regions (flb_set_regions) is stepped alone");
+  // a batch step takes no statistics: refuse rather than leave them unsampled
+  if (h->sample_every > 0 || h->mom_every > 0 || h->corr_every > 0)
+    return fail(FLB_ESTATE, "lattice samples statistics while stepping (flb_set_sampling / "
+                            "flb_set_moment_sampling / flb_set_correlation); stop that before admitting it");
   if (b->precision && (int)h->s != b->precision)
     return fail(FLB_EINVAL, "batch holds precision %d, lattice has %d", b->precision, (int)h->s);
   DevGuard g(b->device);

@@ -393,10 +393,11 @@ class Lattice:
 
 
 class Batch:
-    """A set of lattices advanced together (flb_batch_*): one persistent
-    work-list launch per step for lattices in HBM, whole chunks of steps in
-    LDS for small D1Q3 lattices, chunks captured in a HIP graph.  Results
-    are bit-identical to stepping each member alone."""
+    """A set of lattices advanced together (flb_batch_*): work-list launches
+    (one workgroup per tile of a member) for lattices in HBM, one per step
+    or per two-step pass, whole chunks of steps in LDS for small D1Q3
+    lattices, chunks captured in a HIP graph.  Results are bit-identical to
+    stepping each member alone."""
 
     def __init__(self, chunk=16, use_graph=True, lds_max_bytes=0, workers=0, item_rows=0, tiling=0,
                  stream=None, depth=0, width=0):

@@ -1,7 +1,10 @@
-"""Launch-configuration tuner of the step kernel.
+"""Launch-configuration tuner of the step kernel and of the batch engine.
 
-The step has two kernel variants (plain: one site per thread over the flat
-site index; rows: a block covers tile_x consecutive x of tile_rows rows).
+The step has five kernel variants: plain (one site per thread over the flat
+site index), rows (a block covers tile_x consecutive x of tile_rows rows),
+flat (256 tile_rows consecutive sites of the x-fastest order per block),
+resident (a whole small lattice in one workgroup's LDS) and two (two steps
+per pass over row tiles with a one-site halo).
 All variants compute every site with the same arithmetic in the same order,
 so their results are bit-identical; the tuner times each candidate on the
 GPU, keeps only candidates whose state after a few steps is bit-identical

@@ -113,25 +113,52 @@ def test_batch_noise_plans(precision, plans):
     B.close()
 
 
-def test_batch_members_match_oracle():
-    specs = [s for s in _specs() if s[0] == 1 and s[1][0] <= 1000] + [s for s in _specs() if s[0] == 3]
-    B = flb.Batch(chunk=8)
+@pytest.mark.parametrize("precision", [8, 4])
+@pytest.mark.parametrize("width", [256, 64])
+def test_batch_members_match_oracle(precision, width):
+    # every kind of member against the oracle: D1Q3 in LDS, D2Q5 in two-step
+    # passes over tiles of `width` columns (an odd step count ends with a
+    # single flat step), D3Q7 in flat items; densities >= 5, away from the
+    # non-Lipschitz amplitude at rho = 0
+    specs = [(1, (64,), 1.3, 9.0, 11), (1, (1000,), 0.7, 6.0, 12), (1, (4096,), 1.8, 30.0, 13),
+             (2, (128, 130), 1.1, 8.0, 21), (2, (300, 17), 0.6, 20.0, 22), (2, (257, 64), 1.7, 12.0, 23),
+             (3, (40, 33, 17), 1.1, 5.0, 99)]
+    B = flb.Batch(chunk=8, depth=2, width=width)
     lats, f0s = [], []
     for spec in specs:
-        f0, kw = _member(spec, 8)
-        L = flb.Lattice(spec[0], spec[1], precision=8, **kw)
+        f0, kw = _member(spec, precision)
+        L = flb.Lattice(spec[0], spec[1], precision=precision, **kw)
         L.set_populations(f0)
         B.admit(L)
         lats.append(L)
         f0s.append(f0)
-    B.step(20)
+    B.step(21)
     for L, f0, spec in zip(lats, f0s, specs):
         B.retire(L)
         g = L.get_populations()
         p = oracle.Params(d=spec[0], omega_j=spec[2], seed=spec[4])
-        fo = oracle.run(f0, p, 20)
-        assert report(f"batch member D{spec[0]} {spec[1]}", scaled_error(g, fo, spec[3], p.lattice().w)) <= RTOL[8]
+        fo = oracle.run(f0.astype(np.float64), p, 21)
+        err = scaled_error(g, fo, spec[3], p.lattice().w)
+        assert report(f"batch member fp{8 * precision} width {width} D{spec[0]} {spec[1]}", err) <= RTOL[precision]
         L.close()
+    B.close()
+
+
+def test_admit_refuses_sampling_lattices():
+    # a batch step takes no statistics: a lattice that samples S(k), lattice
+    # sums or correlators while stepping is refused rather than silently
+    # left unsampled
+    B = flb.Batch()
+    for setup in (lambda L: L.set_sampling(5, [(1, 0)]), lambda L: L.set_moment_sampling(3),
+                  lambda L: L.set_correlation(4, [(1, 0)], nlag=2)):
+        L = flb.Lattice(2, (32, 16), precision=4)
+        L.set_populations(np.ones((5, 16, 32), dtype=np.float32))
+        setup(L)
+        with pytest.raises(flb.FlbError) as e:
+            B.admit(L)
+        assert e.value.code == flb.FLB_ESTATE
+        L.close()
+    assert len(B) == 0
     B.close()
 
 

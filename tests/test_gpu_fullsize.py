@@ -34,6 +34,10 @@ def _values_at(f, coords):
 # sites are reported and excluded from the FP32 per-population bound.
 NEAR_ZERO = 1e-3
 HORIZON = 12
+# For FP32 trajectories the amplification reaches the 1e-5 tolerance up to
+# rho ~ 0.02 (a rounding difference d of rho, ~1e-7 of the populations, moves
+# the amplitude by d / (2 sqrt(rho))): the FP32 checks over several steps run
+# at mean density 10 from a smooth start, where no site comes near that.
 
 
 def _check_at(L, f0, p, nsample, tag):
@@ -55,6 +59,35 @@ def _check_at(L, f0, p, nsample, tag):
     return report(f"{tag} after {T} steps, well-conditioned sites", err[:, ok])
 
 
+def _check_boxes(L, f0, p, boxes, tag):
+    """As _check_at for many steps: the oracle evolves whole boxes of sites
+    (origin, extent), one window per box, and every site of every box is
+    compared."""
+    T = L.t
+    g = L.get_populations()
+    lat = p.lattice()
+    d = lat.d
+    rho_eq = float(np.asarray(f0).sum(dtype=np.float64)) / (np.asarray(f0).size // lat.Q)
+    errs, oks = [], []
+    for origin, extent in boxes:
+        ref, minrho = oracle.run_box(f0, lat, p, 0, T, origin, extent, rho_eq=rho_eq, horizon=min(T, HORIZON))
+        idx = np.ix_(*[(origin[a] + np.arange(extent[a])) % L.dims[a] for a in reversed(range(d))])
+        got = g[(slice(None),) + idx]
+        errs.append(scaled_error(got, ref, rho_eq, lat.w).reshape(lat.Q, -1))
+        oks.append((minrho > NEAR_ZERO).ravel())
+    err, ok = np.concatenate(errs, axis=1), np.concatenate(oks)
+    report(f"{tag} after {T} steps at {err.shape[1]} sites in {len(boxes)} boxes (all)", err)
+    if (~ok).any():
+        print(f"[parity] {tag}: {int((~ok).sum())} sites with |rho| < {NEAR_ZERO} in their light cone", flush=True)
+    return report(f"{tag} after {T} steps, well-conditioned sites", err[:, ok])
+
+
+# four boxes of 25 x 20 sites (2000 in all): the far corner (periodic wrap in
+# both axes), the edges and the interior
+BOXES_4096 = [((4085, 4090), (25, 20)), ((0, 1000), (25, 20)), ((2000, 4080), (25, 20)), ((3333, 2222), (25, 20))]
+KVECS = [(k, 0) for k in range(1, 513)] + [(0, k) for k in range(1, 513)]
+
+
 @pytest.mark.parametrize("precision", [4, 8])
 @pytest.mark.parametrize("omega", [0.6, 1.0, 1.8])
 def test_d2q5_4096_sine_rho10(precision, omega):
@@ -66,11 +99,14 @@ def test_d2q5_4096_sine_rho10(precision, omega):
     f0 = inputs.outer(lat.w, rho).astype(np.float32 if precision == 4 else np.float64)
     L.set_populations(f0)
     p = oracle.Params(d=2, omega_j=omega, seed=0)
-    tag = f"D2Q5 4096^2 fp{8 * precision} w={omega}"
-    L.step(1)
+    tag = f"D2Q5 4096^2 fp{8 * precision} w={omega} {cfg['kernel']}"
+    L.step(2)        # one pass of the tuned (two-step) kernel
     assert _check_at(L, f0, p, 20000, tag) <= RTOL[precision]
-    L.step(99)
-    assert _check_at(L, f0, p, 8, tag) <= RTOL[precision]
+    # the benchmark's sampling: sampled passes (which also write the S(k)
+    # partials) interleaved with plain ones
+    L.set_sampling(10, KVECS)
+    L.step(98)
+    assert _check_boxes(L, f0, p, BOXES_4096, tag) <= RTOL[precision]
     m = L.moments()
     # exact in real arithmetic; per site and step the stored populations sum
     # to rho within half an ulp of f_0*, an unbiased error: a random walk
@@ -145,16 +181,32 @@ def test_d2q5_planes_beyond_4_gib():
 
 @pytest.mark.parametrize("precision", [4, 8])
 def test_d2q5_4096_low_density(precision):
+    # rho = 0.1.  FP64: one pass of the tuned two-step kernel against the
+    # oracle.  FP32: the second step of a pass starts from rounded values, and
+    # near rho = 0 the amplitude sqrt(max(rho, 0)) turns that rounding into
+    # differences above 1e-5 (well-conditioned only above rho ~ 0.02); so the
+    # pass is checked as two single steps bit for bit, and the single step,
+    # which starts from identical values, against the oracle
     d, dims = 2, (4096, 4096)
     lat = oracle.make_lattice(d)
     rho = inputs.sine_field(dims, 0.1, 0.1)
     cfg = tune.best_config(d, precision, dims)
+    assert cfg["kernel"] == "two"
     L = gpu_lattice(d, dims, precision, omega=1.0, seed=0, **cfg)
     f0 = inputs.outer(lat.w, rho).astype(np.float32 if precision == 4 else np.float64)
     L.set_populations(f0)
     p = oracle.Params(d=2, omega_j=1.0, seed=0)
-    L.step(1)
-    assert _check_at(L, f0, p, 20000, f"D2Q5 4096^2 rho=0.1 fp{8 * precision}") <= RTOL[precision]
+    L.step(2)        # one pass of the tuned (two-step) kernel
+    if precision == 8:
+        assert _check_at(L, f0, p, 20000, "D2Q5 4096^2 rho=0.1 fp64 two") <= RTOL[8]
+    else:
+        F = gpu_lattice(d, dims, 4, omega=1.0, seed=0, kernel="flat", tile_rows=2, nt_store=1)
+        F.set_populations(f0)
+        F.step(1)
+        assert _check_at(F, f0, p, 20000, "D2Q5 4096^2 rho=0.1 fp32 flat, one step") <= RTOL[4]
+        F.step(1)
+        assert np.array_equal(F.get_populations().view(np.uint8), L.get_populations().view(np.uint8))
+        F.close()
     L.close()
 
 
@@ -171,7 +223,8 @@ def test_d3q7_512_gaussian_fp32():
     L.step(1)
     assert _check_at(L, f0, p, 5000, "D3Q7 512^3 fp32") <= RTOL[4]
     L.step(19)
-    assert _check_at(L, f0, p, 6, "D3Q7 512^3 fp32") <= RTOL[4]
+    boxes = [((505, 506, 507), (13, 13, 12)), ((200, 0, 300), (13, 13, 12))]
+    assert _check_boxes(L, f0, p, boxes, "D3Q7 512^3 fp32") <= RTOL[4]
     m = L.moments()
     bound = 4 * np.finfo(np.float32).eps * 5.0 * np.sqrt(m["nsite"] * 20.0)
     print(f"[mass] D3Q7 512^3 fp32: drift {m['mass'] - m['mass0']:.3e} (bound {bound:.3e})")

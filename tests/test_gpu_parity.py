@@ -71,8 +71,30 @@ def test_low_density_parity(precision):
     g, fo, w, _ = run_both(d, dims, precision, 20, f0, omega=1.0, seed=4, noise="local")
     err = scaled_error(g, fo, 0.1, w)
     frac = float(np.mean(err > RTOL[precision]))
-    report(f"rho=0.1 local 20 steps fp{8 * precision} (fraction above tol {frac:.2e})", err)
-    assert frac < 0.05
+    mx = report(f"rho=0.1 local 20 steps fp{8 * precision} (fraction above tol {frac:.2e})", err)
+    if precision == 8:
+        # a few sites whose density passed within rounding of zero: the
+        # amplitude sqrt(max(rho, 0)) turns a 1e-17 difference of rho into
+        # ~1e-9 of the noise (measured: fraction 5e-4, max 9e-12)
+        assert frac <= 2e-3 and mx <= 1e-10
+    else:
+        assert frac < 0.05
+
+
+@pytest.mark.parametrize("law", ["uniform", "gauss"])
+def test_low_density_fp64_many_steps(law):
+    # rho = 0.1, local noise, FP64, 20 steps: the flat law's variates are
+    # exact in both implementations (2u - 1 of an exact u), the Gaussian
+    # map's carry the rounding of the device's and numpy's logarithm and
+    # sine; either way the only amplification is the non-Lipschitz amplitude
+    # at rho = 0, which stays at a few sites
+    d, dims = 2, SIZES[2]
+    f0 = poisson_state(d, dims, 0.1, seed=11)
+    g, fo, w, _ = run_both(d, dims, 8, 20, f0, omega=1.0, seed=4, noise="local", law=law)
+    err = scaled_error(g, fo, 0.1, w)
+    frac = float(np.mean(err > RTOL[8]))
+    mx = report(f"rho=0.1 local/{law} 20 steps fp64 (fraction above 1e-12: {frac:.2e})", err)
+    assert frac <= 2e-3 and mx <= 1e-10
 
 
 @pytest.mark.parametrize("precision", [8, 4])

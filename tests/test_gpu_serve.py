@@ -5,7 +5,9 @@ alone, bit for bit."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_1606_07801_amd import flb, serve
+from tests.gpu_common import RTOL, report, scaled_error
 
 pytestmark = pytest.mark.gpu
 
@@ -43,6 +45,21 @@ def test_served_results_equal_alone():
     s = serve.summary(S, 1.0)
     assert s["requests"] == len(reqs)
     S.close()
+    # the served results of the requests at mean density >= 5 against the
+    # oracle's FP64 run of the same request from the same initial state
+    checked = 0
+    for r in S.finished:
+        if r.rho < 5.0:
+            continue
+        lat = oracle.make_lattice(r.d)
+        w32 = flb.constants(r.d)[0].astype(np.float32)
+        f0 = np.broadcast_to((w32 * np.float32(r.rho)).reshape((-1,) + (1,) * r.d),
+                             (lat.Q,) + tuple(reversed(r.dims))).astype(np.float64)
+        fo = oracle.run(f0, oracle.Params(d=r.d, omega_j=r.omega, seed=r.seed), r.steps)
+        err = scaled_error(r.result["state"], fo, r.rho, lat.w)
+        assert report(f"served request {r.id} D{r.d} {r.dims} {r.steps} steps", err) <= RTOL[4]
+        checked += 1
+    assert checked >= 4
 
 
 def test_oversized_request_rejected():

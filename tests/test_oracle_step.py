@@ -307,6 +307,55 @@ def test_run_sites_matches_full_run(d, T):
             assert np.abs(g[(slice(None),) + idx] - vals[:, n]).max() < 1e-12
 
 
+@pytest.mark.parametrize("d,T", [(1, 9), (2, 6), (3, 3)])
+def test_run_box_matches_full_run(d, T):
+    # a box that wraps around the periodic edge of every axis, and one larger
+    # than the lattice along x (its window then repeats sites)
+    lat = _lat(d)
+    dims = {1: (30,), 2: (16, 13), 3: (9, 8, 7)}[d]
+    f = _random_state(d, rho=5.0, seed=6, dims=dims)
+    for noise in ("local", "global"):
+        p = oracle.Params(d=d, omega_j=1.2, omega_n=1.7, seed=19, noise=noise)
+        rho_eq = f.sum() / f[0].size
+        g = oracle.run(f, p, T, t0=4, rho_eq=rho_eq)
+        for origin, extent in (([dims[a] - 3 for a in range(d)], [5] * d),
+                               ([1] + [0] * (d - 1), [dims[0] + 4] + [2] * (d - 1))):
+            box = oracle.run_box(f, lat, p, 4, T, origin, extent, rho_eq=rho_eq)
+            idx = np.ix_(*[(origin[a] + np.arange(extent[a])) % dims[a] for a in reversed(range(d))])
+            assert box.shape == (lat.Q,) + tuple(reversed(extent))
+            assert np.abs(box - g[(slice(None),) + idx]).max() < 1e-12
+
+
+@pytest.mark.parametrize("d,T,H", [(1, 8, 5), (2, 6, 4), (2, 3, 3), (3, 3, 2)])
+def test_run_box_light_cone_minimum(d, T, H):
+    # brute force: the full-lattice trajectory's |rho| at every collision of
+    # the last H steps, minimised over each box site's periodic L1 ball of
+    # radius (steps left after that collision)
+    lat = _lat(d)
+    dims = {1: (30,), 2: (16, 13), 3: (9, 8, 7)}[d]
+    f = inputs.gaussian_field(dims, 0.4, 1.0, seed=3)[None] * lat.w.reshape((-1,) + (1,) * d)
+    p = oracle.Params(d=d, omega_j=1.0, seed=2)
+    rhos, g = [], f
+    for t in range(T):
+        rhos.append(np.abs(g.sum(axis=0)))
+        g = oracle.step(g, lat, p, t)
+    origin, extent = [dims[a] - 2 for a in range(d)], [4] * d
+    box, mr = oracle.run_box(f, lat, p, 0, T, origin, extent, horizon=H)
+    assert np.abs(box - g[(slice(None),) + np.ix_(*[(origin[a] + np.arange(4)) % dims[a]
+                                                     for a in reversed(range(d))])]).max() < 1e-12
+    grids = np.meshgrid(*[np.arange(4)] * d, indexing="ij")   # box offsets, array order (.., x)
+    for pos in zip(*[gi.ravel() for gi in grids]):
+        x = [(origin[a] + pos[d - 1 - a]) % dims[a] for a in range(d)]
+        best = np.inf
+        for t in range(T - H, T):
+            r = T - t
+            for q in np.ndindex(*reversed(dims)):          # q in array order (.., y, x)
+                dist = sum(min(abs(q[d - 1 - a] - x[a]), dims[a] - abs(q[d - 1 - a] - x[a])) for a in range(d))
+                if dist <= r:
+                    best = min(best, rhos[t][q])
+        assert mr[pos] == best
+
+
 def test_noise_off_front_follows_the_erf_solution():
     # Sec. IV, non-equilibrium dynamics: at unit rates (D = theta / 2) the
     # deterministic block profile of a y-uniform D2Q5 strip approaches the
