@@ -265,6 +265,23 @@ int flb_set_regions(flb_lattice* h, const uint8_t* region, int32_t nregions, con
  * flb_destroy).  Synchronises the stream. */
 int flb_profile(flb_lattice* h, int32_t axis, double* sum_rho, double* sum_rho2);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * density profile of flb_profile with no allocation and no
+ * synchronisation.  d_sum_rho and d_sum_rho2 are device arrays of n[axis]
+ * doubles, written asynchronously on the handle's stream (read them after
+ * flb_sync or a later event); the values are those flb_profile returns.
+ * The partial sums go to a static device array of
+ * FLB_PROFILE_NOALLOC_MAX_BYTES that the library holds on every GPU it runs
+ * on until the process ends, shared by all calls on that GPU: calls that
+ * overlap on one GPU (on different streams or threads) race, and every call
+ * overwrites what the previous one left there.  The partials need
+ * 16 min(64, n[1] n[2]) n[0] bytes along axis 0 and 16 n[1] n[2] bytes along
+ * axes 1 and 2; above the maximum the call returns FLB_EINVAL and launches
+ * nothing.  The first call on a device looks up the array's address there. */
+#define FLB_PROFILE_NOALLOC_MAX_BYTES (16u << 20)
+int flb_profile_noalloc(flb_lattice* h, int32_t axis, double* d_sum_rho, double* d_sum_rho2);
+
 /* Block until the handle's stream has finished. */
 int flb_sync(flb_lattice* h);
 

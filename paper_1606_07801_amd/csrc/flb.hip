@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -499,20 +500,27 @@ bool sample_due(const flb_lattice* h, int64_t t) {
          (h->sample_every > 0 && t % h->sample_every == 0);
 }
 
-// density profile along `axis` into out (sums of rho, then of rho^2)
+// Bytes of partial sums the density profile along `axis` needs.
+size_t profile_part_bytes(const flb_lattice* h, int axis) {
+  const int64_t nx = h->p.n[0], nrows = h->p.n[1] * h->p.n[2];
+  return axis == 0 ? sizeof(double) * 2 * (size_t)std::min<int64_t>(kColChunks, nrows) * (size_t)nx
+                   : sizeof(double) * 2 * (size_t)nrows;
+}
+
+// density profile along `axis` into out (sums of rho) and out2 (sums of rho^2)
 template <int D, typename T>
-void launch_profile_t(flb_lattice* h, int axis, double* part, double* out) {
+void launch_profile_t(flb_lattice* h, int axis, double* part, double* out, double* out2) {
   const T* g = (const T*)lat_buffer(h, h->cur);
   const int64_t nx = h->p.n[0], ny = h->p.n[1], nz = h->p.n[2], nrows = ny * nz;
   if (axis == 0) {
     const int64_t nchunk = std::min<int64_t>(kColChunks, nrows), rpc = (nrows + nchunk - 1) / nchunk;
     k_prof_cols<D, T><<<dim3((unsigned)((nx + 255) / 256), (unsigned)nchunk), 256, 0, h->stream>>>(g, nx, ny, nz, rpc,
                                                                                                     part);
-    k_prof_cols_final<<<(unsigned)((nx + 255) / 256), 256, 0, h->stream>>>(part, nchunk, nx, out);
+    k_prof_cols_final<<<(unsigned)((nx + 255) / 256), 256, 0, h->stream>>>(part, nchunk, nx, out, out2);
   } else {
     k_prof_rows<D, T><<<(unsigned)nrows, 256, 0, h->stream>>>(g, nx, ny, nz, part);
     const int64_t L = h->p.n[axis];
-    k_prof_yz<<<(unsigned)((L + 255) / 256), 256, 0, h->stream>>>(part, ny, nz, axis, out);
+    k_prof_yz<<<(unsigned)((L + 255) / 256), 256, 0, h->stream>>>(part, ny, nz, axis, out, out2);
   }
 }
 
@@ -543,6 +551,18 @@ void launch_amp(flb_lattice* h) {
     if (h->d == 1) launch_amp_t<1, double>(h, (const double*)g);
     else if (h->d == 2) launch_amp_t<2, double>(h, (const double*)g);
     else launch_amp_t<3, double>(h, (const double*)g);
+  }
+}
+
+void launch_profile(flb_lattice* h, int axis, double* part, double* out, double* out2) {
+  if (h->s == 4) {
+    if (h->d == 1) launch_profile_t<1, float>(h, axis, part, out, out2);
+    else if (h->d == 2) launch_profile_t<2, float>(h, axis, part, out, out2);
+    else launch_profile_t<3, float>(h, axis, part, out, out2);
+  } else {
+    if (h->d == 1) launch_profile_t<1, double>(h, axis, part, out, out2);
+    else if (h->d == 2) launch_profile_t<2, double>(h, axis, part, out, out2);
+    else launch_profile_t<3, double>(h, axis, part, out, out2);
   }
 }
 
@@ -729,6 +749,37 @@ struct DeviceGuard {
     if (prev >= 0) (void)hipSetDevice(prev);
   }
 };
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Static scratch of flb_profile_noalloc: one array per GPU (the module's
+// device global), whose device address is looked up once per device and kept.
+// In host code the array's name is not a device address: only the looked-up
+// pointer is ever passed to kernels.
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)FLB_PROFILE_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// The device address of `scratch` on device `dev` (current), looked up on the
+// first call on that device.
+int scratch_for(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(FLB_EDEVICE, "device index %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e == hipSuccess ? hipErrorInvalidSymbol : e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return FLB_OK;
+}
 
 }  // namespace
 
@@ -1281,19 +1332,28 @@ int flb_profile(flb_lattice* h, int32_t axis, double* sum_rho, double* sum_rho2)
   }
   double* part = (double*)h->prof_mem;
   double* out = part + part_d;
-  if (h->s == 4) {
-    if (h->d == 1) launch_profile_t<1, float>(h, axis, part, out);
-    else if (h->d == 2) launch_profile_t<2, float>(h, axis, part, out);
-    else launch_profile_t<3, float>(h, axis, part, out);
-  } else {
-    if (h->d == 1) launch_profile_t<1, double>(h, axis, part, out);
-    else if (h->d == 2) launch_profile_t<2, double>(h, axis, part, out);
-    else launch_profile_t<3, double>(h, axis, part, out);
-  }
+  launch_profile(h, axis, part, out, out + L);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(sum_rho, out, sizeof(double) * L, hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(hipMemcpyAsync(sum_rho2, out + L, sizeof(double) * L, hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
+  return FLB_OK;
+}
+
+int flb_profile_noalloc(flb_lattice* h, int32_t axis, double* d_sum_rho, double* d_sum_rho2) {
+  if (!h || !d_sum_rho || !d_sum_rho2) return fail(FLB_EINVAL, "NULL argument");
+  if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
+  if (axis < 0 || axis >= h->d) return fail(FLB_EINVAL, "axis %d outside [0, %d)", axis, h->d);
+  const size_t need = profile_part_bytes(h, axis);
+  if (need > kScratchBytes)
+    return fail(FLB_EINVAL, "profile along axis %d needs %zu bytes of partial sums, above the static scratch of %zu",
+                axis, need, kScratchBytes);
+  DeviceGuard g(h->device);
+  void* part = nullptr;
+  const int rc = scratch_for(h->device, &part);
+  if (rc) return rc;
+  launch_profile(h, axis, (double*)part, d_sum_rho, d_sum_rho2);
+  HIP_TRY(hipGetLastError());
   return FLB_OK;
 }
 

@@ -446,9 +446,9 @@ __global__ void __launch_bounds__(256) k_prof_cols(const T* __restrict__ g, int6
   part[(c * nx + x) * 2 + 1] = s2;
 }
 
-// out[x] = sum over chunks (in order) of part, out[nx + x] the same for rho^2
+// out[x] = sum over chunks (in order) of part, out2[x] the same for rho^2
 __global__ void k_prof_cols_final(const double* __restrict__ part, int64_t nchunk, int64_t nx,
-                                  double* __restrict__ out) {
+                                  double* __restrict__ out, double* __restrict__ out2) {
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= nx) return;
   double s = 0, s2 = 0;
@@ -457,7 +457,7 @@ __global__ void k_prof_cols_final(const double* __restrict__ part, int64_t nchun
     s2 += part[(c * nx + x) * 2 + 1];
   }
   out[x] = s;
-  out[nx + x] = s2;
+  out2[x] = s2;
 }
 
 // y / z: one block per row r = y + ny z sums rho and rho^2 over x into rs[2 r + {0, 1}]
@@ -481,9 +481,9 @@ __global__ void __launch_bounds__(256) k_prof_rows(const T* __restrict__ g, int6
   }
 }
 
-// out[c] (and out[L + c] for rho^2) for c along y (axis 1) or z (axis 2)
+// out[c] (and out2[c] for rho^2) for c along y (axis 1) or z (axis 2)
 __global__ void k_prof_yz(const double* __restrict__ rs, int64_t ny, int64_t nz, int axis,
-                          double* __restrict__ out) {
+                          double* __restrict__ out, double* __restrict__ out2) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t L = axis == 1 ? ny : nz, M = axis == 1 ? nz : ny;
   if (c >= L) return;
@@ -494,7 +494,7 @@ __global__ void k_prof_yz(const double* __restrict__ rs, int64_t ny, int64_t nz,
     s2 += rs[2 * r + 1];
   }
   out[c] = s;
-  out[L + c] = s2;
+  out2[c] = s2;
 }
 
 __global__ void k_add(const double* __restrict__ v, double* __restrict__ acc, int n) {

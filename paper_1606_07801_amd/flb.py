@@ -27,7 +27,8 @@ EXPORTS = (
     "flb_create", "flb_set_populations", "flb_get_populations", "flb_step",
     "flb_get_step", "flb_moments", "flb_structure_factor", "flb_set_sampling",
     "flb_set_moment_sampling", "flb_sampled_moments", "flb_set_correlation",
-    "flb_correlation", "flb_fourier_amplitudes", "flb_profile", "flb_set_regions", "flb_sync",
+    "flb_correlation", "flb_fourier_amplitudes", "flb_profile", "flb_set_regions", "flb_profile_noalloc",
+    "flb_sync",
     "flb_destroy",
     "flb_noise_sample", "flb_gauss_map", "flb_batch_create", "flb_batch_admit", "flb_batch_retire",
     "flb_batch_step", "flb_batch_size", "flb_batch_sync", "flb_batch_destroy",
@@ -112,6 +113,7 @@ def load(path=LIB_PATH):
         "flb_fourier_amplitudes": ([vp, dp], ctypes.c_int),
         "flb_profile": ([vp, i32, dp, dp], ctypes.c_int),
         "flb_set_regions": ([vp, vp, i32, dp, dp], ctypes.c_int),
+        "flb_profile_noalloc": ([vp, i32, vp, vp], ctypes.c_int),
         "flb_sync": ([vp], ctypes.c_int),
         "flb_destroy": ([vp], ctypes.c_int),
         "flb_noise_sample": ([i32, i32, i32, u64, i64, i64, i64, vp, vp, vp], ctypes.c_int),
@@ -329,6 +331,12 @@ class Lattice:
         s, s2 = np.zeros(L), np.zeros(L)
         check(load().flb_profile(self.handle, int(axis), s.ctypes.data, s2.ctypes.data))
         return s, s2
+
+    def profile_noalloc(self, axis, out_rho, out_rho2):
+        """The density profile into caller device tensors (n[axis] doubles
+        each), asynchronously, with no allocation (flb_profile_noalloc)."""
+        check(load().flb_profile_noalloc(self.handle, int(axis), _ptr(out_rho), _ptr(out_rho2)))
+        return out_rho, out_rho2
 
     def _moments_dict(self, m):
         Q = self.Q
