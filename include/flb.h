@@ -61,8 +61,20 @@ enum {
 enum { FLB_D1Q3 = 1, FLB_D2Q5 = 2, FLB_D3Q7 = 3 };
 enum { FLB_NOISE_LOCAL = 0, FLB_NOISE_GLOBAL = 1, FLB_NOISE_OFF = 2 };
 enum { FLB_LAW_GAUSS = 0, FLB_LAW_UNIFORM = 1 };
-/* storage scheme: two buffers with pull streaming (the only one so far) */
-enum { FLB_LAYOUT_TWO_BUFFER = 0 };
+/* Storage scheme of the populations (eq. LB's streaming).  TWO_BUFFER: two
+ * buffers of Q N values, pull streaming from one into the other.  AA: one
+ * buffer, stepped in place: a step from the canonical form (even steps
+ * since flb_set_populations) collides every site and stores f_i* in the
+ * slot of the opposite velocity at the same site; the next gathers the
+ * incoming populations from those slots and stores the post-collision values
+ * at the neighbours' own slots, which gives the canonical form again.  Each
+ * site writes exactly the slots it read.  Half the memory, the same traffic,
+ * results bit-identical to TWO_BUFFER.  AA lattices step with the flat or
+ * resident kernels (kernel AUTO, FLAT or RESIDENT; Q N precision < 2^32),
+ * take S(k) samples in a pass of their own, have no regions, and
+ * flb_get_populations into host memory at odd parity allocates a temporary
+ * device buffer of Q N precision bytes (a device destination needs none). */
+enum { FLB_LAYOUT_TWO_BUFFER = 0, FLB_LAYOUT_AA = 1 };
 /* kernel variants of the step (all give bit-identical results).  RESIDENT:
  * one workgroup keeps the whole lattice in LDS and runs up to 65536 steps per
  * launch, with the sampled statistics taken inside; for lattices of at most
@@ -139,7 +151,7 @@ const char* flb_last_error(void);
 int flb_lattice_constants(int32_t model, double theta, double* w, double* m);
 
 /* Bytes of caller-provided device memory a lattice needs: pop_bytes for the
- * populations (one or two buffers of Q * N * precision bytes) and
+ * populations (two buffers of Q * N * precision bytes, one for the AA layout) and
  * work_bytes for the workspace (reductions, structure-factor marginals and
  * accumulators).  Validates the parameters. */
 int flb_required_bytes(const flb_params* p, size_t* pop_bytes, size_t* work_bytes);

@@ -77,7 +77,15 @@ int check_params(const flb_params* p) {
       return fail(FLB_EINVAL, "omega[%d] = %g outside (0, 2)", a, p->omega[a]);
   if (p->noise < 0 || p->noise > 2) return fail(FLB_EINVAL, "noise must be 0 (local), 1 (global) or 2 (off)");
   if (p->noise_law < 0 || p->noise_law > 1) return fail(FLB_EINVAL, "noise_law must be 0 (Gauss) or 1 (uniform)");
-  if (p->layout != FLB_LAYOUT_TWO_BUFFER) return fail(FLB_EINVAL, "layout must be FLB_LAYOUT_TWO_BUFFER");
+  if (p->layout != FLB_LAYOUT_TWO_BUFFER && p->layout != FLB_LAYOUT_AA)
+    return fail(FLB_EINVAL, "layout must be FLB_LAYOUT_TWO_BUFFER or FLB_LAYOUT_AA");
+  if (p->layout == FLB_LAYOUT_AA) {
+    if (p->kernel != FLB_KERNEL_AUTO && p->kernel != FLB_KERNEL_FLAT && p->kernel != FLB_KERNEL_RESIDENT)
+      return fail(FLB_EINVAL, "the AA layout steps with the flat or resident kernels (kernel 0, 3 or 4)");
+    if (n * (2 * d + 1) * p->precision >= 4294967296.0)
+      return fail(FLB_EINVAL, "the AA layout needs Q * N * precision < 2^32 (the flat kernel's 32-bit offsets)");
+    if (p->tile_rows > 8) return fail(FLB_EINVAL, "AA layout (flat kernel): tile_rows <= 8");
+  }
   if (p->kernel < 0 || p->kernel > 5)
     return fail(FLB_EINVAL, "kernel must be 0 (auto), 1 (plain), 2 (rows), 3 (flat), 4 (resident) or 5 (two-step)");
   if (p->kernel == FLB_KERNEL_TWO_STEP &&
@@ -174,7 +182,11 @@ WorkLayout work_layout(const flb_params& p) {
 
 namespace flb {
 
-char* lat_buffer(flb_lattice* h, int which) { return h->pop + (size_t)which * h->plane; }
+// the two buffers of the pull scheme; the single buffer of the AA layout
+char* lat_buffer(flb_lattice* h, int which) { return h->aa ? h->pop : h->pop + (size_t)which * h->plane; }
+
+// form of the stored state: pull storage, or the AA parity (cur counts steps mod 2)
+int state_form(const flb_lattice* h) { return !h->aa ? kFormPull : (h->cur ? kFormAAS : kFormAAC); }
 
 // ---------------------------------------------------------------------------
 // step launch
@@ -186,6 +198,26 @@ int launch_step_t(flb_lattice* h, const T* g, T* out, uint32_t step, hipStream_t
     return 0;
   }
   const KParams<T> P = make_kparams<T>(h->p, h->rho_eq);
+  if (h->aa) {  // in place on the single buffer, from the current parity's form
+    T* a = out;
+    const int ry = h->p.tile_rows ? h->p.tile_rows : (D == 2 ? 2 : 1);
+    const int64_t nb = (h->n + 256 * ry - 1) / (256 * ry);
+    const bool nt = h->p.nt_store != 0;
+    const bool even = state_form(h) == kFormAAC;
+#define FLB_AA(RYV)                                                                                     \
+  (even ? (nt ? (void)(k_step_flat_aa<D, T, RYV, true, kFormAAC><<<(unsigned)nb, 256, 0, st>>>(a, P, step))  \
+              : (void)(k_step_flat_aa<D, T, RYV, false, kFormAAC><<<(unsigned)nb, 256, 0, st>>>(a, P, step))) \
+        : (nt ? (void)(k_step_flat_aa<D, T, RYV, true, kFormAAS><<<(unsigned)nb, 256, 0, st>>>(a, P, step))  \
+              : (void)(k_step_flat_aa<D, T, RYV, false, kFormAAS><<<(unsigned)nb, 256, 0, st>>>(a, P, step))))
+    switch (ry) {
+      case 1: FLB_AA(1); break;
+      case 2: FLB_AA(2); break;
+      case 4: FLB_AA(4); break;
+      default: FLB_AA(8); break;
+    }
+#undef FLB_AA
+    return FLB_OK;
+  }
   // single steps of a two-step lattice take the flat kernel (2 rows per tile)
   const int kern = h->p.kernel == FLB_KERNEL_AUTO ? FLB_KERNEL_ROWS
                    : (h->p.kernel == FLB_KERNEL_TWO_STEP ? FLB_KERNEL_FLAT : h->p.kernel);
@@ -252,13 +284,13 @@ int launch_step(flb_lattice* h, const void* g, void* out, uint32_t step, hipStre
 // canonical conversions
 template <typename T>
 void launch_convert_t(int d, bool to_canon, const T* src, T* dst, int64_t nx, int64_t ny, int64_t nz,
-                      hipStream_t st) {
+                      hipStream_t st, int form) {
   const int64_t n = nx * ny * nz;
   const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
   if (to_canon) {
-    if (d == 1) k_to_canonical<1, T><<<nb, 256, 0, st>>>(src, dst, nx, ny, nz);
-    else if (d == 2) k_to_canonical<2, T><<<nb, 256, 0, st>>>(src, dst, nx, ny, nz);
-    else k_to_canonical<3, T><<<nb, 256, 0, st>>>(src, dst, nx, ny, nz);
+    if (d == 1) k_to_canonical<1, T><<<nb, 256, 0, st>>>(src, dst, nx, ny, nz, form);
+    else if (d == 2) k_to_canonical<2, T><<<nb, 256, 0, st>>>(src, dst, nx, ny, nz, form);
+    else k_to_canonical<3, T><<<nb, 256, 0, st>>>(src, dst, nx, ny, nz, form);
   } else {
     if (d == 1) k_from_canonical<1, T><<<nb, 256, 0, st>>>(src, dst, nx, ny, nz);
     else if (d == 2) k_from_canonical<2, T><<<nb, 256, 0, st>>>(src, dst, nx, ny, nz);
@@ -266,11 +298,15 @@ void launch_convert_t(int d, bool to_canon, const T* src, T* dst, int64_t nx, in
   }
 }
 
-void launch_convert(flb_lattice* h, bool to_canon, const void* src, void* dst) {
+// to_canon: the canonical state from src stored in `form`; else the pull
+// storage form from canonical src
+void launch_convert(flb_lattice* h, bool to_canon, const void* src, void* dst, int form = kFormPull) {
   if (h->s == 4)
-    launch_convert_t<float>(h->d, to_canon, (const float*)src, (float*)dst, h->p.n[0], h->p.n[1], h->p.n[2], h->stream);
+    launch_convert_t<float>(h->d, to_canon, (const float*)src, (float*)dst, h->p.n[0], h->p.n[1], h->p.n[2], h->stream,
+                            form);
   else
-    launch_convert_t<double>(h->d, to_canon, (const double*)src, (double*)dst, h->p.n[0], h->p.n[1], h->p.n[2], h->stream);
+    launch_convert_t<double>(h->d, to_canon, (const double*)src, (double*)dst, h->p.n[0], h->p.n[1], h->p.n[2],
+                             h->stream, form);
 }
 
 // lattice sums into work.red_out (device)
@@ -279,7 +315,8 @@ void launch_moments_t(flb_lattice* h, const T* g) {
   const int64_t nb = std::min<int64_t>((h->n + 255) / 256, kRedBlocks);
   double* part = (double*)(h->work + h->wl.red_part);
   double* out = (double*)(h->work + h->wl.red_out);
-  k_moments_partial<D, T><<<(unsigned)nb, 256, 0, h->stream>>>(g, h->p.n[0], h->p.n[1], h->p.n[2], part);
+  k_moments_partial<D, T><<<(unsigned)nb, 256, 0, h->stream>>>(g, h->p.n[0], h->p.n[1], h->p.n[2], part,
+                                                                state_form(h));
   k_moments_final<<<kNV, 256, 0, h->stream>>>(part, (int)nb, out);
 }
 
@@ -372,6 +409,8 @@ void launch_resident(flb_lattice* h, int c, size_t lds, int corr_lds) {
   ResArgs A{};
   A.gin = lat_buffer(h, h->cur);
   A.gout = lat_buffer(h, (h->cur + c) & 1);
+  A.form_in = state_form(h);
+  A.form_out = !h->aa ? kFormPull : (((h->cur + c) & 1) ? kFormAAS : kFormAAC);
   A.nx = (int32_t)h->p.n[0];
   A.ny = (int32_t)h->p.n[1];
   A.nz = (int32_t)h->p.n[2];
@@ -515,10 +554,10 @@ void launch_profile_t(flb_lattice* h, int axis, double* part, double* out, doubl
   if (axis == 0) {
     const int64_t nchunk = std::min<int64_t>(kColChunks, nrows), rpc = (nrows + nchunk - 1) / nchunk;
     k_prof_cols<D, T><<<dim3((unsigned)((nx + 255) / 256), (unsigned)nchunk), 256, 0, h->stream>>>(g, nx, ny, nz, rpc,
-                                                                                                    part);
+                                                                                                    part, state_form(h));
     k_prof_cols_final<<<(unsigned)((nx + 255) / 256), 256, 0, h->stream>>>(part, nchunk, nx, out, out2);
   } else {
-    k_prof_rows<D, T><<<(unsigned)nrows, 256, 0, h->stream>>>(g, nx, ny, nz, part);
+    k_prof_rows<D, T><<<(unsigned)nrows, 256, 0, h->stream>>>(g, nx, ny, nz, part, state_form(h));
     const int64_t L = h->p.n[axis];
     k_prof_yz<<<(unsigned)((L + 255) / 256), 256, 0, h->stream>>>(part, ny, nz, axis, out, out2);
   }
@@ -534,7 +573,7 @@ void launch_amp_t(flb_lattice* h, const T* g) {
   k_amp_partial<D, T><<<grid, 256, 0, h->stream>>>(g, h->p.n[0], h->p.n[1], h->p.n[2],
                                                     (const double*)(m + h->corr_off[1]),
                                                     (const int32_t*)(m + h->corr_off[0]), h->corr_nk,
-                                                    h->corr_nsb, (double*)(m + h->corr_off[2]));
+                                                    h->corr_nsb, (double*)(m + h->corr_off[2]), state_form(h));
   const int64_t nv = (int64_t)h->corr_nk * 2 * Q;
   k_amp_final<<<(unsigned)((nv + 255) / 256), 256, 0, h->stream>>>((const double*)(m + h->corr_off[2]),
                                                                    h->corr_nsb, h->corr_nk, 2 * Q,
@@ -661,8 +700,9 @@ void launch_sk_t(flb_lattice* h, int set, bool from_step) {
                                                     (const double*)(w + h->wl.colbig), ntr, nx, nchunk,
                                                     (double*)(w + h->wl.marg));
     } else {
-      k_row_sums<D, T><<<(unsigned)nrows, 256, 0, st>>>(g, nx, ny, nz, rowsum);
-      k_col_partial<D, T><<<dim3((unsigned)((nx + 255) / 256), (unsigned)nchunk), 256, 0, st>>>(g, nx, ny, nz, rpc, colpart);
+      k_row_sums<D, T><<<(unsigned)nrows, 256, 0, st>>>(g, nx, ny, nz, rowsum, state_form(h));
+      k_col_partial<D, T><<<dim3((unsigned)((nx + 255) / 256), (unsigned)nchunk), 256, 0, st>>>(g, nx, ny, nz, rpc, colpart,
+                                                                                               state_form(h));
     }
     axis_sk(h, set, nchunk, from_step);
   }
@@ -671,7 +711,7 @@ void launch_sk_t(flb_lattice* h, int set, bool from_step) {
     const int64_t chunk = (h->n + nchunk - 1) / nchunk;
     double* part = (double*)(w + h->wl.skpart);
     k_sk_direct_partial<D, T><<<dim3((unsigned)nchunk, (unsigned)h->ngen[set]), 256, 0, st>>>(
-        g, nx, ny, nz, (const int64_t*)(w + h->wl.kv[set]), h->rho_eq, chunk, part);
+        g, nx, ny, nz, (const int64_t*)(w + h->wl.kv[set]), h->rho_eq, chunk, part, state_form(h));
     k_sk_direct_final<<<(unsigned)((h->ngen[set] + 63) / 64), 64, 0, st>>>(
         part, nchunk, h->ngen[set], (const int32_t*)(w + h->wl.slot_gen[set]),
         (const int64_t*)(w + h->wl.kv[set]), h->rho_eq, (double)h->n, sval);
@@ -833,7 +873,7 @@ int flb_required_bytes(const flb_params* p, size_t* pop_bytes, size_t* work_byte
   if (rc) return rc;
   const size_t n = (size_t)(p->n[0] * p->n[1] * p->n[2]);
   const size_t Q = 2 * p->model + 1;
-  if (pop_bytes) *pop_bytes = 2 * Q * n * (size_t)p->precision;
+  if (pop_bytes) *pop_bytes = (p->layout == FLB_LAYOUT_AA ? 1 : 2) * Q * n * (size_t)p->precision;
   if (work_bytes) *work_bytes = work_layout(*p).total;
   return FLB_OK;
 }
@@ -859,6 +899,7 @@ int flb_create(const flb_params* p, void* d_pop, size_t pop_bytes, void* d_work,
   h->s = (size_t)p->precision;
   h->plane = (size_t)h->Q * h->n * h->s;
   h->pop = (char*)d_pop;
+  h->aa = p->layout == FLB_LAYOUT_AA;
   h->cur = 0;
   h->stream = (hipStream_t)hip_stream;
   h->step = 0;
@@ -952,13 +993,19 @@ int flb_set_populations(flb_lattice* h, const void* src, int src_on_device, int6
   if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
   if (step < 0) return fail(FLB_EINVAL, "step must be >= 0");
   DeviceGuard g(h->device);
-  // stage the canonical state in the spare buffer, then pull it back into
-  // storage form in the current buffer
-  const int spare = 1 - h->cur;
-  HIP_TRY(hipMemcpyAsync(lat_buffer(h, spare), src, h->plane,
-                         src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream));
-  launch_convert(h, false, lat_buffer(h, spare), lat_buffer(h, h->cur));
-  HIP_TRY(hipGetLastError());
+  if (h->aa) {  // the canonical state is the AA layout's even-parity form
+    h->cur = 0;
+    HIP_TRY(hipMemcpyAsync(h->pop, src, h->plane, src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                           h->stream));
+  } else {
+    // stage the canonical state in the spare buffer, then pull it back into
+    // storage form in the current buffer
+    const int spare = 1 - h->cur;
+    HIP_TRY(hipMemcpyAsync(lat_buffer(h, spare), src, h->plane,
+                           src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream));
+    launch_convert(h, false, lat_buffer(h, spare), lat_buffer(h, h->cur));
+    HIP_TRY(hipGetLastError());
+  }
   launch_moments(h);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(h->stage->red, h->work + h->wl.red_out, sizeof(double) * kNV, hipMemcpyDeviceToHost, h->stream));
@@ -977,6 +1024,26 @@ int flb_get_populations(flb_lattice* h, void* dst, int dst_on_device) {
   if (!h || !dst) return fail(FLB_EINVAL, "NULL argument");
   if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
   DeviceGuard g(h->device);
+  if (h->aa) {
+    if (state_form(h) == kFormAAC) {  // already canonical
+      HIP_TRY(hipMemcpyAsync(dst, h->pop, h->plane, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                             h->stream));
+    } else if (dst_on_device) {  // gather straight into the caller's buffer
+      launch_convert(h, true, h->pop, dst, kFormAAS);
+      HIP_TRY(hipGetLastError());
+    } else {  // no spare buffer in this layout: a temporary one
+      void* tmp = nullptr;
+      HIP_TRY(hipMalloc(&tmp, h->plane));
+      launch_convert(h, true, h->pop, tmp, kFormAAS);
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess) e = hipMemcpyAsync(dst, tmp, h->plane, hipMemcpyDeviceToHost, h->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+      (void)hipFree(tmp);
+      if (e != hipSuccess) return hip_fail(e, "AA-layout readback");
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return FLB_OK;
+  }
   const int spare = 1 - h->cur;
   launch_convert(h, true, lat_buffer(h, h->cur), lat_buffer(h, spare));
   HIP_TRY(hipGetLastError());
@@ -1138,7 +1205,8 @@ int flb_set_sampling(flb_lattice* h, int64_t every, const int32_t* kvec, int32_t
   const int rc = flb_structure_factor(h, kvec, nk, FLB_SK_RESET, nullptr);
   if (rc) return rc;
   h->sample_every = every;
-  h->sample_fused = h->d >= 2 && h->ngen[1] == 0;
+  // the sampled step kernels write the pull storage form: two buffers only
+  h->sample_fused = h->d >= 2 && h->ngen[1] == 0 && !h->aa;
   return FLB_OK;
 }
 
@@ -1283,6 +1351,7 @@ int flb_set_regions(flb_lattice* h, const uint8_t* region, int32_t nregions, con
     h->reg_n = 0;
     return FLB_OK;
   }
+  if (h->aa) return fail(FLB_EINVAL, "regions step with the per-site two-buffer kernel: not with the AA layout");
   if (!region || !theta || !omega) return fail(FLB_EINVAL, "NULL argument");
   if (nregions < 1 || nregions > kMaxRegions) return fail(FLB_EINVAL, "need 1 <= nregions <= %d", kMaxRegions);
   for (int r = 0; r < nregions; ++r) {

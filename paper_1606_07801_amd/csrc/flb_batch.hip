@@ -28,8 +28,9 @@ struct BatchRep {
   int64_t tiles_x;  // tiles of kBatchTX columns
   int64_t nrows;    // ny * nz
   int64_t step0;    // steps completed at the start of the chunk
-  int32_t cur0;     // buffer holding the state at the start of the chunk
+  int32_t cur0;     // buffer holding the state at the start of the chunk (AA layout: its parity)
   int32_t depth;    // 2: D2Q5 member stepped in two-step passes (one buffer swap per pass)
+  int32_t aa;       // single-buffer AA layout (stepped in place, depth 1)
 };
 
 // Buffer holding a member's state k steps into a chunk: one swap per step,
@@ -61,6 +62,13 @@ __global__ void __launch_bounds__(256) k_batch_flat(const BatchRep<T>* __restric
     const KParams<T> P = R.P;
     const uint32_t step = (uint32_t)((uint64_t)(R.step0 + k) & 0xFFFFFFFFull);
     const int par = member_parity(R, k);
+    if (R.aa) {  // in place, from the form of this step's parity
+      if (par == 0)
+        flat_tile_aa<D, T, kBatchRY, true, kFormAAC>((T*)R.pop, P, step, tile * 256 * kBatchRY, threadIdx.x);
+      else
+        flat_tile_aa<D, T, kBatchRY, true, kFormAAS>((T*)R.pop, P, step, tile * 256 * kBatchRY, threadIdx.x);
+      continue;
+    }
     const T* g = (const T*)(R.pop + par * R.plane);
     T* h = (T*)(R.pop + (par ^ 1) * R.plane);
     flat_tile<D, T, kBatchRY, true>(g, h, P, step, tile * 256 * kBatchRY, threadIdx.x);
@@ -130,14 +138,18 @@ __global__ void __launch_bounds__(256) k_batch_lds_d1(const BatchRep<T>* __restr
   T* s1 = s0 + L;
   T* s2 = s1 + L;
   const int tid = threadIdx.x;
-  const T* g = (const T*)(R.pop + R.cur0 * R.plane);
-  for (int x = tid; x < L; x += 256) {  // f_i(x) = g_i(x - v_i)
+  // pull storage: f_i(x) = g_i(x - v_i); AA layout (one buffer, read whole
+  // into LDS before anything is stored): the form of the parity
+  const T* g = (const T*)(R.pop + (R.aa ? 0 : R.cur0 * R.plane));
+  const bool cin = R.aa && R.cur0 == 0, swin = R.aa && R.cur0 == 1;
+  for (int x = tid; x < L; x += 256) {
     s0[x] = g[x];
-    s1[x] = g[L + (x == 0 ? L - 1 : x - 1)];
-    s2[x] = g[2 * L + (x == L - 1 ? 0 : x + 1)];
+    s1[x] = cin ? g[L + x] : g[(swin ? 2 : 1) * L + (x == 0 ? L - 1 : x - 1)];
+    s2[x] = cin ? g[2 * L + x] : g[(swin ? 1 : 2) * L + (x == L - 1 ? 0 : x + 1)];
   }
   __syncthreads();
-  T* out = (T*)(R.pop + ((R.cur0 + c) & 1) * R.plane);
+  T* out = (T*)(R.pop + (R.aa ? 0 : ((R.cur0 + c) & 1) * R.plane));
+  const bool cout_ = R.aa && ((R.cur0 + c) & 1) == 0, swout = R.aa && !cout_;
   for (int k = 0; k < c; ++k) {
     const uint32_t step = (uint32_t)((uint64_t)(R.step0 + k) & 0xFFFFFFFFull);
     T f[SPT][3];
@@ -166,10 +178,10 @@ __global__ void __launch_bounds__(256) k_batch_lds_d1(const BatchRep<T>* __restr
 #pragma unroll
       for (int j = 0; j < SPT; ++j) {
         const int x = tid + 256 * j;
-        if (x < L) {
+        if (x < L) {  // pull storage at x; AA form S: opposite slots at x; form C: pushed
           out[x] = f[j][0];
-          out[L + x] = f[j][1];
-          out[2 * L + x] = f[j][2];
+          out[(swout ? 2 : 1) * L + (cout_ ? (x == L - 1 ? 0 : x + 1) : x)] = f[j][1];
+          out[(swout ? 1 : 2) * L + (cout_ ? (x == 0 ? L - 1 : x - 1) : x)] = f[j][2];
         }
       }
     }
@@ -265,6 +277,7 @@ int rebuild_t(flb_batch* b) {
     R.nrows = h->p.n[1] * h->p.n[2];
     R.step0 = h->step;
     R.cur0 = h->cur;
+    R.aa = h->aa ? 1 : 0;
     const int64_t state_bytes = (int64_t)h->Q * h->n * (int64_t)sizeof(T);
     if (h->d == 1 && lds_max > 0 && state_bytes <= lds_max && h->n <= 256 * 16) {
       lds.push_back(i);
@@ -272,8 +285,10 @@ int rebuild_t(flb_batch* b) {
       continue;
     }
     const int64_t item_rows = (int64_t)kBatchRY * b->sub;
-    const bool flat = b->o.tiling == 0 && (int64_t)h->plane < (1ll << 32);
-    if (b->o.depth == 2 && h->d == 2 && (int64_t)h->plane < (1ll << 32)) {
+    // AA members step in place with the flat items (their layout has no
+    // second buffer for a two-step pass)
+    const bool flat = (b->o.tiling == 0 || h->aa) && (int64_t)h->plane < (1ll << 32);
+    if (b->o.depth == 2 && h->d == 2 && !h->aa && (int64_t)h->plane < (1ll << 32)) {
       R.depth = 2;
       two_lg = two_lg && h->p.noise == FLB_NOISE_LOCAL && h->p.noise_law == FLB_LAW_GAUSS;
       const int64_t tw = b->o.width;
@@ -553,7 +568,7 @@ int flb_batch_step(flb_batch* b, int64_t nsteps) {
   HIP_TRY(hipGetLastError());
   // buffer swaps of each member, chunk by chunk (depth-2 D2Q5 members swap once per pass)
   for (flb_lattice* h : b->members) {
-    const bool two = b->o.depth == 2 && h->d == 2 && (int64_t)h->plane < (1ll << 32);
+    const bool two = b->o.depth == 2 && h->d == 2 && !h->aa && (int64_t)h->plane < (1ll << 32);
     const int64_t swaps = two ? chunks * ((c + 1) / 2) + (rem + 1) / 2 : nsteps;
     h->step += nsteps;
     h->cur = (int)((h->cur + swaps) & 1);

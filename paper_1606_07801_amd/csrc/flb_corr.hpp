@@ -23,7 +23,7 @@ template <int D, typename T>
 __global__ void __launch_bounds__(256) k_amp_partial(const T* __restrict__ g, int64_t nx, int64_t ny,
                                                      int64_t nz, const double* __restrict__ tw,
                                                      const int32_t* __restrict__ kinfo, int nk, int nsb,
-                                                     double* __restrict__ part) {
+                                                     double* __restrict__ part, int form = kFormPull) {
   constexpr int Q = 2 * D + 1;
   constexpr int KC = kCorrKC;
   __shared__ double lds[4];
@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(256) k_amp_partial(const T* __restrict__ g, in
     const int64_t x = s % nx, yz = s / nx, y = yz % ny, z = yz / ny;
     const Nbr b = neighbours(x, y, z, nx, ny, nz);
     T fv[Q];
-    gather<D, T>(g, n, b, fv);
+    gather<D, T>(g, n, b, fv, form);
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
       double cr = twx[2 * ((kx[c] * x) % nx)], ci = twx[2 * ((kx[c] * x) % nx) + 1];

@@ -53,8 +53,9 @@ struct flb_lattice {
   int64_t n;
   size_t s;           // bytes per real
   size_t plane;       // bytes of one buffer (Q * n * s)
-  char* pop;          // two buffers
-  int cur;            // buffer holding the current state
+  char* pop;          // two buffers, or one (AA layout)
+  bool aa;            // single-buffer AA layout
+  int cur;            // buffer holding the current state; AA: steps since set, mod 2
   char* work;
   bool own_work;
   flb::WorkLayout wl;

@@ -37,20 +37,37 @@ __device__ __forceinline__ Nbr neighbours(int64_t x, int64_t y, int64_t z, int64
   return r;
 }
 
-// f_i(x, t) = g_i(x - v_i)
+// Forms in which a state is stored (plane i holds n values, x fastest):
+//   kFormPull  two-buffer storage: g_i(x) = f_i*(x, t - 1), so f_i(x, t) = g_i(x - v_i)
+//   kFormAAC   single buffer after an even number of steps: A_i(x) = f_i(x, t)
+//   kFormAAS   single buffer after an odd number: A_opp(i)(x) = f_i*(x, t - 1), so
+//              f_i(x, t) = A_opp(i)(x - v_i), opp(i) the population moving the other way
+// One AA step from form C collides every site in place and stores f_i* in the
+// opposite slot (form S); one from form S gathers f_i(x) = A_opp(i)(x - v_i),
+// collides and stores f_i* at A_i(x + v_i) (form C).  In both, the slots a
+// site writes are exactly the slots it read, so a step runs in place.
+enum StateForm : int { kFormPull = 0, kFormAAC = 1, kFormAAS = 2 };
+
+// f_i(x, t) of one site from its stored state
 template <int D, typename T>
 __device__ __forceinline__ void gather(const T* __restrict__ g, int64_t n, const Nbr& b,
-                                       T (&f)[2 * D + 1]) {
+                                       T (&f)[2 * D + 1], int form = kFormPull) {
+  if (form == kFormAAC) {
+#pragma unroll
+    for (int i = 0; i < 2 * D + 1; ++i) f[i] = g[i * n + b.s];
+    return;
+  }
+  const bool sw = form == kFormAAS;  // plane of population i: opp(i)
   f[0] = g[b.s];
-  f[1] = g[n + b.sxm];
-  f[2] = g[2 * n + b.sxp];
+  f[1] = g[(sw ? 2 : 1) * n + b.sxm];
+  f[2] = g[(sw ? 1 : 2) * n + b.sxp];
   if constexpr (D >= 2) {
-    f[3] = g[3 * n + b.sym];
-    f[4] = g[4 * n + b.syp];
+    f[3] = g[(sw ? 4 : 3) * n + b.sym];
+    f[4] = g[(sw ? 3 : 4) * n + b.syp];
   }
   if constexpr (D >= 3) {
-    f[5] = g[5 * n + b.szm];
-    f[6] = g[6 * n + b.szp];
+    f[5] = g[(sw ? 6 : 5) * n + b.szm];
+    f[6] = g[(sw ? 5 : 6) * n + b.szp];
   }
 }
 
@@ -211,6 +228,79 @@ __device__ __forceinline__ void rows_tile_pipe(const T* __restrict__ g, T* __res
   }
 }
 
+// Flat-order offsets of one site of a flat tile: the site and its periodic
+// neighbours along each axis (sxm = the site at x - 1, and so on), all as
+// 32-bit site indices.
+struct FlatSite {
+  uint32_t s, sxm, sxp, sym, syp, szm, szp;
+};
+
+// Coordinates of a flat tile's first site, uniform over the workgroup (scalar
+// unit).  When a row holds at least the tile's 256 RY sites a lane crosses at
+// most one row end, so its coordinates follow by one compare instead of a
+// per-lane division (quarter-rate integer multiplies).
+struct FlatOrigin {
+  uint32_t nx, ny, nz, n, nxy, x0, r0, y0, z0;
+  bool wide;
+};
+
+template <int D, int RY, typename T>
+__device__ __forceinline__ FlatOrigin flat_origin(const KParams<T>& P, uint32_t s0u) {
+  FlatOrigin o;
+  o.nx = (uint32_t)P.nx;
+  o.ny = (uint32_t)P.ny;
+  o.nz = (uint32_t)P.nz;
+  o.n = (uint32_t)P.n;  // n * S < 2^32 (checked by the caller)
+  o.nxy = o.nx * o.ny;
+  o.x0 = s0u % o.nx;
+  o.r0 = s0u / o.nx;
+  o.y0 = D == 3 ? o.r0 % o.ny : o.r0;
+  o.z0 = D == 3 ? o.r0 / o.ny : 0;
+  o.wide = o.nx >= 256u * RY;
+  return o;
+}
+
+// The site s = s0 + off of the tile (s < n).
+template <int D>
+__device__ __forceinline__ FlatSite flat_site(const FlatOrigin& o, uint32_t s, uint32_t off) {
+  uint32_t x, rest, yw = 0, zw = 0;
+  if (o.wide) {
+    x = o.x0 + off;
+    const uint32_t c = x >= o.nx ? 1u : 0u;
+    x -= c ? o.nx : 0u;
+    rest = o.r0 + c;
+    if constexpr (D == 3) {
+      yw = o.y0 + c;
+      const uint32_t c2 = yw >= o.ny ? 1u : 0u;
+      yw -= c2 ? o.ny : 0u;
+      zw = o.z0 + c2;
+    }
+  } else {
+    x = s % o.nx;
+    rest = s / o.nx;
+    if constexpr (D == 3) {
+      yw = rest % o.ny;
+      zw = rest / o.ny;
+    }
+  }
+  FlatSite f;
+  f.s = s;
+  f.sxm = x == 0 ? s + o.nx - 1 : s - 1;
+  f.sxp = x == o.nx - 1 ? s + 1 - o.nx : s + 1;
+  f.sym = f.syp = f.szm = f.szp = s;
+  if constexpr (D >= 2) {
+    const uint32_t y = D == 2 ? rest : yw;
+    f.sym = y == 0 ? s + o.nxy - o.nx : s - o.nx;
+    f.syp = y == o.ny - 1 ? s + o.nx - o.nxy : s + o.nx;
+  }
+  if constexpr (D >= 3) {
+    const uint32_t z = zw;
+    f.szm = z == 0 ? s + o.n - o.nxy : s - o.nxy;
+    f.szp = z == o.nz - 1 ? s + o.nxy - o.n : s + o.nxy;
+  }
+  return f;
+}
+
 // Flat tile: RY blocks of 256 consecutive sites s0 + j * 256 + lane of the
 // row-major site order, so a lattice's sites fill every lane except in its
 // last tile.  Each lane derives (x, y, z) and its periodic neighbours
@@ -221,60 +311,27 @@ __device__ __forceinline__ void flat_tile(const T* __restrict__ g, T* __restrict
                                           uint32_t lane) {
   constexpr int Q = 2 * D + 1;
   constexpr uint32_t S = sizeof(T);
-  const uint32_t nx = (uint32_t)P.nx, ny = (uint32_t)P.ny, nz = (uint32_t)P.nz;
-  const uint32_t n = (uint32_t)P.n;               // n * S < 2^32 (checked by the caller)
-  const uint32_t nxy = nx * ny;
-  // coordinates of the tile's first site, uniform over the workgroup (scalar
-  // unit); when a row holds at least the tile's 256 RY sites a lane crosses
-  // at most one row end, so its coordinates follow by one compare instead of
-  // a per-lane division (quarter-rate integer multiplies)
-  const uint32_t s0u = (uint32_t)s0;
-  const uint32_t x0 = s0u % nx, r0 = s0u / nx;
-  const uint32_t y0 = D == 3 ? r0 % ny : r0, z0 = D == 3 ? r0 / ny : 0;
-  const bool wide = nx >= 256u * RY;
+  const FlatOrigin o = flat_origin<D, RY>(P, (uint32_t)s0);
+  const uint32_t n = o.n;
   T f[RY][Q];
   uint32_t sj[RY];
 #pragma unroll
   for (int j = 0; j < RY; ++j) {
     const uint32_t off = (uint32_t)j * 256u + lane;
-    const uint32_t s = s0u + off;
+    const uint32_t s = (uint32_t)s0 + off;
     sj[j] = s;
     if (s < n) {
-      uint32_t x, rest, yw = 0, zw = 0;
-      if (wide) {
-        x = x0 + off;
-        const uint32_t c = x >= nx ? 1u : 0u;
-        x -= c ? nx : 0u;
-        rest = r0 + c;
-        if constexpr (D == 3) {
-          yw = y0 + c;
-          const uint32_t c2 = yw >= ny ? 1u : 0u;
-          yw -= c2 ? ny : 0u;
-          zw = z0 + c2;
-        }
-      } else {
-        x = s % nx;
-        rest = s / nx;
-        if constexpr (D == 3) {
-          yw = rest % ny;
-          zw = rest / ny;
-        }
-      }
-      const uint32_t sxm = x == 0 ? s + nx - 1 : s - 1, sxp = x == nx - 1 ? s + 1 - nx : s + 1;
+      const FlatSite b = flat_site<D>(o, s, off);
       f[j][0] = ld_at(g, s * S);
-      f[j][1] = ld_at(g + n, sxm * S);
-      f[j][2] = ld_at(g + 2 * (int64_t)n, sxp * S);
+      f[j][1] = ld_at(g + n, b.sxm * S);
+      f[j][2] = ld_at(g + 2 * (int64_t)n, b.sxp * S);
       if constexpr (D >= 2) {
-        const uint32_t y = D == 2 ? rest : yw;
-        const uint32_t sym = y == 0 ? s + nxy - nx : s - nx, syp = y == ny - 1 ? s + nx - nxy : s + nx;
-        f[j][3] = ld_at(g + 3 * (int64_t)n, sym * S);
-        f[j][4] = ld_at(g + 4 * (int64_t)n, syp * S);
-        if constexpr (D >= 3) {
-          const uint32_t z = zw;
-          const uint32_t szm = z == 0 ? s + n - nxy : s - nxy, szp = z == nz - 1 ? s + nxy - n : s + nxy;
-          f[j][5] = ld_at(g + 5 * (int64_t)n, szm * S);
-          f[j][6] = ld_at(g + 6 * (int64_t)n, szp * S);
-        }
+        f[j][3] = ld_at(g + 3 * (int64_t)n, b.sym * S);
+        f[j][4] = ld_at(g + 4 * (int64_t)n, b.syp * S);
+      }
+      if constexpr (D >= 3) {
+        f[j][5] = ld_at(g + 5 * (int64_t)n, b.szm * S);
+        f[j][6] = ld_at(g + 6 * (int64_t)n, b.szp * S);
       }
     }
   }
@@ -286,6 +343,71 @@ __device__ __forceinline__ void flat_tile(const T* __restrict__ g, T* __restrict
       for (int i = 0; i < Q; ++i) st_at<T, NT>(h + i * (int64_t)n, sj[j] * S, f[j][i]);
     }
   }
+}
+
+// Plane of the AA single buffer that population i of a site reads in form
+// FORM, and the neighbour offset it reads at; the step then writes the
+// population's post-collision value to the plane and offset of opp(i)'s read
+// (form C -> S: the opposite plane at the site; form S -> C: plane i at the
+// neighbour x + v_i), so every site writes exactly the slots it read.
+template <int D>
+__device__ __forceinline__ uint32_t aa_read_off(const FlatSite& b, int i, int form) {
+  if (form == kFormAAC) return b.s;
+  switch (i) {
+    case 1: return b.sxm;
+    case 2: return b.sxp;
+    case 3: return b.sym;
+    case 4: return b.syp;
+    case 5: return b.szm;
+    case 6: return b.szp;
+    default: return b.s;
+  }
+}
+
+__device__ __forceinline__ int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+// One AA step of a flat tile in place on the single buffer a: from form
+// kFormAAC (even parity) to kFormAAS, or from kFormAAS to kFormAAC.  The
+// collisions are those of flat_tile on the same pre-collision values.
+template <int D, typename T, int RY, bool NT, int FORM>
+__device__ __forceinline__ void flat_tile_aa(T* a, const KParams<T>& P, uint32_t step, int64_t s0, uint32_t lane) {
+  constexpr int Q = 2 * D + 1;
+  constexpr uint32_t S = sizeof(T);
+  const FlatOrigin o = flat_origin<D, RY>(P, (uint32_t)s0);
+  const uint32_t n = o.n;
+  T f[RY][Q];
+  FlatSite bj[RY];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) {
+    const uint32_t off = (uint32_t)j * 256u + lane;
+    const uint32_t s = (uint32_t)s0 + off;
+    bj[j].s = s;
+    if (s < n) {
+      bj[j] = flat_site<D>(o, s, off);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const int pl = FORM == kFormAAC ? i : opp(i);
+        f[j][i] = ld_at((const T*)a + pl * (int64_t)n, aa_read_off<D>(bj[j], i, FORM) * S);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < RY; ++j) {
+    if (bj[j].s < n) {
+      Collide<D, T>::run(f[j], P, (uint64_t)bj[j].s, step);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        // f_i* goes where opp(i) was read
+        const int pl = FORM == kFormAAC ? opp(i) : i;
+        st_at<T, NT>(a + pl * (int64_t)n, aa_read_off<D>(bj[j], opp(i), FORM) * S, f[j][i]);
+      }
+    }
+  }
+}
+
+template <int D, typename T, int RY, bool NT, int FORM>
+__global__ void __launch_bounds__(256) k_step_flat_aa(T* a, KParams<T> P, uint32_t step) {
+  flat_tile_aa<D, T, RY, NT, FORM>(a, P, step, (int64_t)blockIdx.x * 256 * RY, threadIdx.x);
 }
 
 // Sum over the 64 lanes of a wave with DPP lane moves (no LDS): quad swaps,
@@ -531,7 +653,7 @@ __global__ void __launch_bounds__(1024) k_step_rows(const T* __restrict__ g, T* 
 // out: f_i(x) = g_i(x - v_i);  in: g_i(x - v_i) = f_i(x).
 template <int D, typename T>
 __global__ void k_to_canonical(const T* __restrict__ g, T* __restrict__ f, int64_t nx, int64_t ny,
-                               int64_t nz) {
+                               int64_t nz, int form = kFormPull) {
   constexpr int Q = 2 * D + 1;
   const int64_t n = nx * ny * nz;
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
@@ -539,7 +661,7 @@ __global__ void k_to_canonical(const T* __restrict__ g, T* __restrict__ f, int64
     const int64_t x = s % nx, rest = s / nx, y = rest % ny, z = rest / ny;
     const Nbr b = neighbours(x, y, z, nx, ny, nz);
     T v[Q];
-    gather<D, T>(g, n, b, v);
+    gather<D, T>(g, n, b, v, form);
 #pragma unroll
     for (int i = 0; i < Q; ++i) f[i * n + s] = v[i];
   }

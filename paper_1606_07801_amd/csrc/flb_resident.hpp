@@ -33,8 +33,11 @@ constexpr int kResMaxSites = 4 * kResThreads;
 constexpr int kResMaxChunk = 1 << 16;         // steps per launch
 
 struct ResArgs {
-  const void* gin;  // storage-form buffer holding the state at step0
-  void* gout;       // storage-form buffer receiving the state at step0 + nsteps
+  const void* gin;  // buffer holding the state at step0, in form form_in
+  void* gout;       // buffer receiving the state at step0 + nsteps, in form form_out
+                    // (the same buffer for the single-buffer layout: the whole
+                    // state is in LDS before the first store)
+  int32_t form_in, form_out;
   int32_t nx, ny, nz;
   int32_t nsteps;
   int64_t step0;
@@ -560,7 +563,7 @@ __global__ void __launch_bounds__(NT) k_resident(KParams<T> P, ResArgs A) {
     if (s < N) {
       const Nbr b = neighbours(cx[j], cy[j], cz[j], nx, ny, nz);
       T fv[Q];
-      gather<D, T>(g, N, b, fv);
+      gather<D, T>(g, N, b, fv, A.form_in);
 #pragma unroll
       for (int i = 0; i < Q; ++i) st[i * N + s] = fv[i];
     }
@@ -623,12 +626,34 @@ __global__ void __launch_bounds__(NT) k_resident(KParams<T> P, ResArgs A) {
           }
         }
       }
-    } else {
+    } else if (A.form_out == kFormPull) {
 #pragma unroll
       for (int j = 0; j < SPT; ++j) {
         if (sites[j] < N) {
 #pragma unroll
           for (int i = 0; i < Q; ++i) out[(int64_t)i * N + sites[j]] = f[j][i];
+        }
+      }
+    } else {
+      // single buffer: form S keeps f_i* in the opposite slot at the site,
+      // form C pushes it to slot i of the neighbour x + v_i
+      const bool sw = A.form_out == kFormAAS;
+#pragma unroll
+      for (int j = 0; j < SPT; ++j) {
+        const int s = sites[j];
+        if (s < N) {
+          const Nbr b = neighbours(cx[j], cy[j], cz[j], nx, ny, nz);
+          out[s] = f[j][0];
+          out[(int64_t)(sw ? 2 : 1) * N + (sw ? s : b.sxp)] = f[j][1];
+          out[(int64_t)(sw ? 1 : 2) * N + (sw ? s : b.sxm)] = f[j][2];
+          if constexpr (D >= 2) {
+            out[(int64_t)(sw ? 4 : 3) * N + (sw ? s : b.syp)] = f[j][3];
+            out[(int64_t)(sw ? 3 : 4) * N + (sw ? s : b.sym)] = f[j][4];
+          }
+          if constexpr (D >= 3) {
+            out[(int64_t)(sw ? 6 : 5) * N + (sw ? s : b.szp)] = f[j][5];
+            out[(int64_t)(sw ? 5 : 6) * N + (sw ? s : b.szm)] = f[j][6];
+          }
         }
       }
     }

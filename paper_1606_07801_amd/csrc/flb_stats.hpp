@@ -35,7 +35,7 @@ constexpr int kNV = 40;
 template <int D, typename T>
 __global__ void __launch_bounds__(256) k_moments_partial(const T* __restrict__ g, int64_t nx,
                                                          int64_t ny, int64_t nz,
-                                                         double* __restrict__ part) {
+                                                         double* __restrict__ part, int form = kFormPull) {
   constexpr int Q = 2 * D + 1;
   constexpr int NFF = Q * (Q + 1) / 2;
   __shared__ double lds[4];
@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(256) k_moments_partial(const T* __restrict__ g
     const int64_t x = s % nx, rest = s / nx, y = rest % ny, z = rest / ny;
     const Nbr b = neighbours(x, y, z, nx, ny, nz);
     T fv[Q];
-    gather<D, T>(g, n, b, fv);
+    gather<D, T>(g, n, b, fv, form);
     double f[Q];
     double rho = 0;
 #pragma unroll
@@ -113,10 +113,10 @@ __global__ void __launch_bounds__(256) k_moments_final(const double* __restrict_
 template <int D, typename T>
 __device__ __forceinline__ double site_density(const T* __restrict__ g, int64_t n, int64_t x,
                                                int64_t y, int64_t z, int64_t nx, int64_t ny,
-                                               int64_t nz) {
+                                               int64_t nz, int form = kFormPull) {
   const Nbr b = neighbours(x, y, z, nx, ny, nz);
   T fv[2 * D + 1];
-  gather<D, T>(g, n, b, fv);
+  gather<D, T>(g, n, b, fv, form);
   double rho = 0;
 #pragma unroll
   for (int i = 0; i < 2 * D + 1; ++i) rho += (double)fv[i];
@@ -126,14 +126,14 @@ __device__ __forceinline__ double site_density(const T* __restrict__ g, int64_t 
 // Row sums: rowsum[row] = sum_x rho(x, row), one block per row.
 template <int D, typename T>
 __global__ void __launch_bounds__(256) k_row_sums(const T* __restrict__ g, int64_t nx, int64_t ny,
-                                                  int64_t nz, double* __restrict__ rowsum) {
+                                                  int64_t nz, double* __restrict__ rowsum, int form = kFormPull) {
   __shared__ double lds[4];
   const int64_t n = nx * ny * nz;
   const int64_t row = blockIdx.x;
   const int64_t y = row % ny, z = row / ny;
   double acc = 0;
   for (int64_t x = threadIdx.x; x < nx; x += blockDim.x)
-    acc += site_density<D, T>(g, n, x, y, z, nx, ny, nz);
+    acc += site_density<D, T>(g, n, x, y, z, nx, ny, nz, form);
   const double v = block_sum256(acc, lds);
   if (threadIdx.x == 0) rowsum[row] = v;
 }
@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(256) k_row_sums(const T* __restrict__ g, int64
 template <int D, typename T>
 __global__ void __launch_bounds__(256) k_col_partial(const T* __restrict__ g, int64_t nx, int64_t ny,
                                                      int64_t nz, int64_t rows_per_chunk,
-                                                     double* __restrict__ colpart) {
+                                                     double* __restrict__ colpart, int form = kFormPull) {
   const int64_t n = nx * ny * nz;
   const int64_t nrows = ny * nz;
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(256) k_col_partial(const T* __restrict__ g, in
   const int64_t r1 = r0 + rows_per_chunk < nrows ? r0 + rows_per_chunk : nrows;
   double acc = 0;
   for (int64_t row = r0; row < r1; ++row)
-    acc += site_density<D, T>(g, n, x, row % ny, row / ny, nx, ny, nz);
+    acc += site_density<D, T>(g, n, x, row % ny, row / ny, nx, ny, nz, form);
   colpart[c * nx + x] = acc;
 }
 
@@ -377,7 +377,7 @@ __global__ void __launch_bounds__(256) k_sk_direct_partial(const T* __restrict__
                                                            int64_t ny, int64_t nz,
                                                            const int64_t* __restrict__ kv,
                                                            double mean, int64_t chunk,
-                                                           double* __restrict__ partial) {
+                                                           double* __restrict__ partial, int form = kFormPull) {
   __shared__ double lds[4];
   const int64_t n = nx * ny * nz;
   const int64_t c = blockIdx.x, j = blockIdx.y, nchunk = gridDim.x;
@@ -386,7 +386,7 @@ __global__ void __launch_bounds__(256) k_sk_direct_partial(const T* __restrict__
   double re = 0, im = 0;
   for (int64_t s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
     const int64_t x = s % nx, rest = s / nx, y = rest % ny, z = rest / ny;
-    const double v = site_density<D, T>(g, n, x, y, z, nx, ny, nz) - mean;
+    const double v = site_density<D, T>(g, n, x, y, z, nx, ny, nz, form) - mean;
     // phase / (2 pi) = sum_a ((k_a x_a) mod L_a) / L_a, reduced mod 1
     double ph = (double)((kx * x) % nx) / (double)nx + (double)((ky * y) % ny) / (double)ny +
                 (double)((kz * z) % nz) / (double)nz;
@@ -431,14 +431,15 @@ __global__ void k_sk_direct_final(const double* __restrict__ partial, int64_t nc
 // x: chunk c of the rows gives part[(c * nx + x) * 2 + {0, 1}].
 template <int D, typename T>
 __global__ void __launch_bounds__(256) k_prof_cols(const T* __restrict__ g, int64_t nx, int64_t ny,
-                                                   int64_t nz, int64_t rpc, double* __restrict__ part) {
+                                                   int64_t nz, int64_t rpc, double* __restrict__ part,
+                                                   int form = kFormPull) {
   const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (x >= nx) return;
   const int64_t n = nx * ny * nz, nrows = ny * nz;
   const int64_t c = blockIdx.y, r0 = c * rpc, r1 = r0 + rpc < nrows ? r0 + rpc : nrows;
   double s = 0, s2 = 0;
   for (int64_t r = r0; r < r1; ++r) {
-    const double rho = site_density<D, T>(g, n, x, r % ny, r / ny, nx, ny, nz);
+    const double rho = site_density<D, T>(g, n, x, r % ny, r / ny, nx, ny, nz, form);
     s += rho;
     s2 += rho * rho;
   }
@@ -463,12 +464,12 @@ __global__ void k_prof_cols_final(const double* __restrict__ part, int64_t nchun
 // y / z: one block per row r = y + ny z sums rho and rho^2 over x into rs[2 r + {0, 1}]
 template <int D, typename T>
 __global__ void __launch_bounds__(256) k_prof_rows(const T* __restrict__ g, int64_t nx, int64_t ny,
-                                                   int64_t nz, double* __restrict__ rs) {
+                                                   int64_t nz, double* __restrict__ rs, int form = kFormPull) {
   __shared__ double lds[4];
   const int64_t r = blockIdx.x, n = nx * ny * nz;
   double s = 0, s2 = 0;
   for (int64_t x = threadIdx.x; x < nx; x += blockDim.x) {
-    const double rho = site_density<D, T>(g, n, x, r % ny, r / ny, nx, ny, nz);
+    const double rho = site_density<D, T>(g, n, x, r % ny, r / ny, nx, ny, nz, form);
     s += rho;
     s2 += rho * rho;
   }

@@ -19,6 +19,7 @@ MODELS = {"D1Q3": 1, "D2Q5": 2, "D3Q7": 3, 1: 1, 2: 2, 3: 3}
 NOISE = {"local": 0, "global": 1, "off": 2}
 LAWS = {"gauss": 0, "uniform": 1}
 KERNELS = {"auto": 0, "plain": 1, "rows": 2, "flat": 3, "resident": 4, "two": 5}
+LAYOUTS = {"two": 0, "aa": 1}
 SK_SNAPSHOT, SK_SAMPLE, SK_READ, SK_RESET = 0, 1, 2, 3
 
 # exported symbols, in the order include/flb.h declares them
@@ -160,7 +161,7 @@ def constants(model, theta=0.0):
 
 def make_params(model, dims, precision=4, theta=0.0, omega=1.0, omega_n=0.0, omega_s=0.0,
                 seed=0, noise="local", law="gauss", kernel="auto", tile_x=0, tile_rows=0, nt_store=0,
-                pipeline=0):
+                pipeline=0, layout="two"):
     d = MODELS[model]
     dims = tuple(int(x) for x in dims) + (1,) * (3 - len(dims))
     p = Params()
@@ -173,7 +174,7 @@ def make_params(model, dims, precision=4, theta=0.0, omega=1.0, omega_n=0.0, ome
     p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
     p.noise = NOISE[noise]
     p.noise_law = LAWS[law]
-    p.layout = 0
+    p.layout = LAYOUTS[layout]
     p.kernel = KERNELS[kernel]
     p.tile_x = int(tile_x)
     p.tile_rows = int(tile_rows)

@@ -28,7 +28,7 @@ from . import flb, inputs
 
 class Request:
     __slots__ = ("id", "arrival", "d", "dims", "steps", "omega", "rho", "seed", "precision",
-                 "lat", "bytes", "start", "done", "remaining", "result", "error", "keep_state")
+                 "lat", "bytes", "start", "done", "remaining", "result", "error", "keep_state", "layout")
 
     def __init__(self, rid, arrival, d, dims, steps, omega, rho, seed, precision=4, keep_state=False):
         self.id, self.arrival, self.d, self.dims = rid, float(arrival), int(d), tuple(int(x) for x in dims)
@@ -41,6 +41,7 @@ class Request:
         self.result = None
         self.error = None
         self.keep_state = keep_state
+        self.layout = "two"
 
     @property
     def sites(self):
@@ -53,9 +54,24 @@ class Request:
 
 
 def request_bytes(req):
-    p = flb.make_params(req.d, req.dims, precision=req.precision, omega=req.omega, seed=req.seed)
+    p = flb.make_params(req.d, req.dims, precision=req.precision, omega=req.omega, seed=req.seed,
+                        layout=req.layout)
     pop, work = flb.required_bytes(p)
     return pop + work + 512
+
+
+def pick_layout(req, policy):
+    """Storage layout of a request.  "two": two buffers for every request;
+    "aa": one buffer (AA layout, half the population memory) for every
+    request; "auto": one buffer except for D2Q5 lattices the two-step pass
+    can take (their two buffers buy a pass per two steps), so the models
+    that step one pass per step anyway hold half the memory."""
+    if policy == "two":
+        return "two"
+    if policy == "aa":
+        return "aa" if req.sites * (2 * req.d + 1) * req.precision < (1 << 32) else "two"
+    two_step = req.d == 2 and req.sites * 5 * req.precision < (1 << 32)
+    return "two" if two_step or req.sites * (2 * req.d + 1) * req.precision >= (1 << 32) else "aa"
 
 
 def initial_state(torch, req, device):
@@ -70,7 +86,7 @@ def initial_state(torch, req, device):
 
 def start_request(torch, req, device):
     L = flb.Lattice(req.d, req.dims, precision=req.precision, omega=req.omega, seed=req.seed,
-                    noise="local")
+                    noise="local", layout=req.layout)
     f0 = initial_state(torch, req, device)
     L.set_populations(f0)
     del f0
@@ -93,7 +109,7 @@ def finish_request(req):
 class Server:
     """Admission by HBM budget, continuous batching by ticks."""
 
-    def __init__(self, budget_bytes=None, tick_steps=64, chunk=None, use_graph=True, device=None):
+    def __init__(self, budget_bytes=None, tick_steps=64, chunk=None, use_graph=True, device=None, layout="auto"):
         import torch
         self.torch = torch
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -114,8 +130,12 @@ class Server:
         self.rejected = []
         self.ticks = 0
         self.site_updates = 0
+        self.layout = layout
+        self.peak_active = 0
+        self.active_ticks = 0      # sum over ticks of the number of active requests
 
     def submit(self, req):
+        req.layout = pick_layout(req, self.layout)
         req.bytes = request_bytes(req)
         if req.bytes > self.budget:
             req.error = f"needs {req.bytes} bytes, budget is {self.budget}"
@@ -154,6 +174,8 @@ class Server:
         self.batch.step(n)
         self.batch.sync()
         self.ticks += 1
+        self.peak_active = max(self.peak_active, len(self.active))
+        self.active_ticks += len(self.active)
         t = time.perf_counter()
         for r in list(self.active):
             r.remaining -= n
@@ -200,7 +222,9 @@ def summary(server, makespan):
         "p50_latency_s": round(float(np.percentile(lat, 50)), 4) if len(lat) else None,
         "p99_latency_s": round(float(np.percentile(lat, 99)), 4) if len(lat) else None,
         "mlups": round(ups / makespan / 1e6, 1) if makespan > 0 else None,
-        "ticks": server.ticks,
+        "ticks": server.ticks, "layout": server.layout, "peak_resident": server.peak_active,
+        "mean_resident": round(server.active_ticks / server.ticks, 2) if server.ticks else 0,
+        "budget_gb": round(server.budget / 2 ** 30, 2),
     }
 
 
@@ -218,12 +242,14 @@ def main():
     ap.add_argument("--max-steps", type=float, default=1e5)
     ap.add_argument("--budget-gb", type=float, default=0.0)
     ap.add_argument("--tick", type=int, default=64)
+    ap.add_argument("--layout", default="auto", choices=["auto", "aa", "two"])
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
     reqs = make_requests(args.requests, args.rate, args.seed, sites=(1e3, args.max_sites),
                          steps=(1e2, args.max_steps))
-    S = Server(budget_bytes=int(args.budget_gb * 2 ** 30) if args.budget_gb else None, tick_steps=args.tick)
+    S = Server(budget_bytes=int(args.budget_gb * 2 ** 30) if args.budget_gb else None, tick_steps=args.tick,
+               layout=args.layout)
     mk = S.run(reqs)
     out = summary(S, mk)
     out.update({"rate_per_s": args.rate, "work_site_updates": S.site_updates,

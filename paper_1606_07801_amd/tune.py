@@ -56,12 +56,19 @@ def _load():
         return {}
 
 
-def best_config(d, precision, dims):
+def best_config(d, precision, dims, layout="two"):
     """Kernel keyword arguments for a lattice: the cached tuning result, or
     the defaults.  The two-step and flat kernels address a population plane
     with 32-bit byte offsets and accept only Q N precision < 2^32; larger
-    lattices of a size class tuned to one of them take the defaults."""
+    lattices of a size class tuned to one of them take the defaults.  The
+    single-buffer AA layout steps with the flat kernel (resident when tiny):
+    its tiles follow a tuned flat entry, else the flat defaults."""
     ent = _load().get(_key(d, precision, dims))
+    if layout == "aa":
+        if size_class(dims) == "tiny":
+            return dict(kernel="auto", layout="aa")
+        ry = ent["tile_rows"] if ent and ent["kernel"] == "flat" else (2 if d == 2 else 1)
+        return dict(kernel="flat", tile_rows=ry, nt_store=1, layout="aa")
     if size_class(dims) == "tiny" and (not ent or ent["kernel"] == "resident"):
         return dict(kernel="auto")      # resident when the lattice fits the LDS, else rows
     if ent and ent["kernel"] in ("two", "flat") and (2 * d + 1) * int(np.prod(dims)) * precision >= 1 << 32:
