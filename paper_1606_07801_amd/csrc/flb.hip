@@ -204,18 +204,24 @@ int launch_step_t(flb_lattice* h, const T* g, T* out, uint32_t step, hipStream_t
     const int64_t nb = (h->n + 256 * ry - 1) / (256 * ry);
     const bool nt = h->p.nt_store != 0;
     const bool even = state_form(h) == kFormAAC;
-#define FLB_AA(RYV)                                                                                     \
-  (even ? (nt ? (void)(k_step_flat_aa<D, T, RYV, true, kFormAAC><<<(unsigned)nb, 256, 0, st>>>(a, P, step))  \
-              : (void)(k_step_flat_aa<D, T, RYV, false, kFormAAC><<<(unsigned)nb, 256, 0, st>>>(a, P, step))) \
-        : (nt ? (void)(k_step_flat_aa<D, T, RYV, true, kFormAAS><<<(unsigned)nb, 256, 0, st>>>(a, P, step))  \
-              : (void)(k_step_flat_aa<D, T, RYV, false, kFormAAS><<<(unsigned)nb, 256, 0, st>>>(a, P, step))))
+    const bool lg = h->p.noise == FLB_NOISE_LOCAL && h->p.noise_law == FLB_LAW_GAUSS;
+#define FLB_AA1(NTV, FV)                                                                                        \
+  (lg ? (void)(k_step_flat_aa<D, T, RYV, NTV, FV, kPlanLocalGauss><<<(unsigned)nb, 256, 0, st>>>(a, P, step)) \
+      : (void)(k_step_flat_aa<D, T, RYV, NTV, FV><<<(unsigned)nb, 256, 0, st>>>(a, P, step)))
+#define FLB_AA(RYV_)                                                                      \
+  {                                                                                       \
+    constexpr int RYV = RYV_;                                                             \
+    if (even) { if (nt) FLB_AA1(true, kFormAAC); else FLB_AA1(false, kFormAAC); }         \
+    else { if (nt) FLB_AA1(true, kFormAAS); else FLB_AA1(false, kFormAAS); }              \
+  }
     switch (ry) {
-      case 1: FLB_AA(1); break;
-      case 2: FLB_AA(2); break;
-      case 4: FLB_AA(4); break;
-      default: FLB_AA(8); break;
+      case 1: FLB_AA(1) break;
+      case 2: FLB_AA(2) break;
+      case 4: FLB_AA(4) break;
+      default: FLB_AA(8) break;
     }
 #undef FLB_AA
+#undef FLB_AA1
     return FLB_OK;
   }
   // single steps of a two-step lattice take the flat kernel (2 rows per tile)
@@ -228,9 +234,13 @@ int launch_step_t(flb_lattice* h, const T* g, T* out, uint32_t step, hipStream_t
     const int ry = h->p.kernel == FLB_KERNEL_TWO_STEP ? 2 : (h->p.tile_rows ? h->p.tile_rows : 2);
     const int64_t nb = (h->n + 256 * ry - 1) / (256 * ry);
     const bool nt = h->p.nt_store != 0;
-#define FLB_FLAT(RYV)                                                                     \
-  (nt ? (void)(k_step_flat<D, T, RYV, true><<<(unsigned)nb, 256, 0, st>>>(g, out, P, step)) \
-      : (void)(k_step_flat<D, T, RYV, false><<<(unsigned)nb, 256, 0, st>>>(g, out, P, step)))
+    // local Gaussian noise (the default) takes the instances with that noise plan fixed at compile time
+    const bool lg = h->p.noise == FLB_NOISE_LOCAL && h->p.noise_law == FLB_LAW_GAUSS;
+#define FLB_FLAT(RYV)                                                                                             \
+  (lg ? (nt ? (void)(k_step_flat<D, T, RYV, true, kPlanLocalGauss><<<(unsigned)nb, 256, 0, st>>>(g, out, P, step))  \
+            : (void)(k_step_flat<D, T, RYV, false, kPlanLocalGauss><<<(unsigned)nb, 256, 0, st>>>(g, out, P, step))) \
+      : (nt ? (void)(k_step_flat<D, T, RYV, true><<<(unsigned)nb, 256, 0, st>>>(g, out, P, step))                   \
+            : (void)(k_step_flat<D, T, RYV, false><<<(unsigned)nb, 256, 0, st>>>(g, out, P, step))))
     switch (ry) {
       case 1: FLB_FLAT(1); break;
       case 2: FLB_FLAT(2); break;

@@ -50,7 +50,7 @@ constexpr int kBatchRY = 2;
 // smaller than the list the workgroups persist and stride over it.
 // Flat work list: item w covers sites item_tile[w] * 256 * kBatchRY ... of
 // member item_rep[w] (flat_tile), so narrow lattices keep every lane busy.
-template <int D, typename T>
+template <int D, typename T, int NP = kPlanRuntime>
 __global__ void __launch_bounds__(256) k_batch_flat(const BatchRep<T>* __restrict__ reps,
                                                     const int32_t* __restrict__ item_rep,
                                                     const int32_t* __restrict__ item_tile,
@@ -64,14 +64,14 @@ __global__ void __launch_bounds__(256) k_batch_flat(const BatchRep<T>* __restric
     const int par = member_parity(R, k);
     if (R.aa) {  // in place, from the form of this step's parity
       if (par == 0)
-        flat_tile_aa<D, T, kBatchRY, true, kFormAAC>((T*)R.pop, P, step, tile * 256 * kBatchRY, threadIdx.x);
+        flat_tile_aa<D, T, kBatchRY, true, kFormAAC, NP>((T*)R.pop, P, step, tile * 256 * kBatchRY, threadIdx.x);
       else
-        flat_tile_aa<D, T, kBatchRY, true, kFormAAS>((T*)R.pop, P, step, tile * 256 * kBatchRY, threadIdx.x);
+        flat_tile_aa<D, T, kBatchRY, true, kFormAAS, NP>((T*)R.pop, P, step, tile * 256 * kBatchRY, threadIdx.x);
       continue;
     }
     const T* g = (const T*)(R.pop + par * R.plane);
     T* h = (T*)(R.pop + (par ^ 1) * R.plane);
-    flat_tile<D, T, kBatchRY, true>(g, h, P, step, tile * 256 * kBatchRY, threadIdx.x);
+    flat_tile<D, T, kBatchRY, true, NP>(g, h, P, step, tile * 256 * kBatchRY, threadIdx.x);
   }
 }
 
@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(kBatchTX) k_batch_rows(const BatchRep<T>* __re
 // destinations.  The last step stores the post-collision populations at
 // their collision sites in the member's other-parity buffer, the storage form
 // flb_step leaves.
-template <typename T, int SPT>
+template <typename T, int SPT, int NP = kPlanRuntime>
 __global__ void __launch_bounds__(256) k_batch_lds_d1(const BatchRep<T>* __restrict__ reps,
                                                       const int32_t* __restrict__ lds_rep, int c) {
   extern __shared__ unsigned char smem_raw[];
@@ -160,7 +160,7 @@ __global__ void __launch_bounds__(256) k_batch_lds_d1(const BatchRep<T>* __restr
         f[j][0] = s0[x];
         f[j][1] = s1[x];
         f[j][2] = s2[x];
-        Collide<1, T>::run(f[j], P, (uint64_t)x, step);
+        Collide<1, T, NP>::run(f[j], P, (uint64_t)x, step);
       }
     }
     __syncthreads();
@@ -222,6 +222,8 @@ struct flb_batch {
   int nreps;
   int sub;  // sub-tiles of kBatchRY rows per work item
   bool two_lg;  // every depth-2 member has local Gaussian noise (compile-time noise plan)
+  bool flat_lg;  // every flat-item member has local Gaussian noise
+  bool lds_lg;   // every LDS member has local Gaussian noise
   hipGraphExec_t exec;
   int exec_chunk;
 };
@@ -265,7 +267,7 @@ int rebuild_t(flb_batch* b) {
   std::vector<int32_t> lds;
   int64_t lmax = 0;
   const int64_t lds_max = b->o.lds_max_bytes < 0 ? -1 : (b->o.lds_max_bytes ? b->o.lds_max_bytes : 65536);
-  bool two_lg = true;
+  bool two_lg = true, flat_lg = true, lds_lg = true;
   for (int i = 0; i < n; ++i) {
     flb_lattice* h = b->members[i];
     BatchRep<T>& R = reps[i];
@@ -279,7 +281,9 @@ int rebuild_t(flb_batch* b) {
     R.cur0 = h->cur;
     R.aa = h->aa ? 1 : 0;
     const int64_t state_bytes = (int64_t)h->Q * h->n * (int64_t)sizeof(T);
+    const bool lg = h->p.noise == FLB_NOISE_LOCAL && h->p.noise_law == FLB_LAW_GAUSS;
     if (h->d == 1 && lds_max > 0 && state_bytes <= lds_max && h->n <= 256 * 16) {
+      lds_lg = lds_lg && lg;
       lds.push_back(i);
       lmax = std::max<int64_t>(lmax, h->n);
       continue;
@@ -304,6 +308,7 @@ int rebuild_t(flb_batch* b) {
         items[8][0].push_back(i);
         items[8][1].push_back((int32_t)t);
       }
+      flat_lg = flat_lg && lg;  // their odd trailing step takes the flat items
       continue;
     }
     R.depth = 1;
@@ -312,6 +317,7 @@ int rebuild_t(flb_batch* b) {
                                : R.tiles_x * ((R.nrows + item_rows - 1) / item_rows);
     if (ntile >= (1ll << 31)) return fail(FLB_EINVAL, "member %d has too many tiles", i);
     const int cls = h->d + (flat ? 3 : 0);
+    if (flat) flat_lg = flat_lg && lg;
     for (int64_t t = 0; t < ntile; ++t) {
       items[cls][0].push_back(i);
       items[cls][1].push_back((int32_t)t);
@@ -347,6 +353,8 @@ int rebuild_t(flb_batch* b) {
   b->lds_bytes = (size_t)(3 * lmax * (int64_t)sizeof(T));
   b->nreps = n;
   b->two_lg = two_lg;
+  b->flat_lg = flat_lg;
+  b->lds_lg = lds_lg;
   b->dirty = false;
   drop_graph(b);
   return FLB_OK;
@@ -359,13 +367,17 @@ void enqueue_chunk_t(flb_batch* b, int c) {
   if (b->nlds > 0) {
     const int32_t* lr = (const int32_t*)(b->d_table + b->off_lds);
     const dim3 grid(b->nlds), block(256);
+#define FLB_LDS(SV)                                                                                  \
+  (b->lds_lg ? (void)(k_batch_lds_d1<T, SV, kPlanLocalGauss><<<grid, block, b->lds_bytes, st>>>(reps, lr, c)) \
+             : (void)(k_batch_lds_d1<T, SV><<<grid, block, b->lds_bytes, st>>>(reps, lr, c)))
     switch (b->lds_spt) {
-      case 1: k_batch_lds_d1<T, 1><<<grid, block, b->lds_bytes, st>>>(reps, lr, c); break;
-      case 2: k_batch_lds_d1<T, 2><<<grid, block, b->lds_bytes, st>>>(reps, lr, c); break;
-      case 4: k_batch_lds_d1<T, 4><<<grid, block, b->lds_bytes, st>>>(reps, lr, c); break;
-      case 8: k_batch_lds_d1<T, 8><<<grid, block, b->lds_bytes, st>>>(reps, lr, c); break;
-      default: k_batch_lds_d1<T, 16><<<grid, block, b->lds_bytes, st>>>(reps, lr, c); break;
+      case 1: FLB_LDS(1); break;
+      case 2: FLB_LDS(2); break;
+      case 4: FLB_LDS(4); break;
+      case 8: FLB_LDS(8); break;
+      default: FLB_LDS(16); break;
     }
+#undef FLB_LDS
   }
   if (b->nitems[7] > 0) {  // depth-2 members: two-step passes, a single flat step for an odd chunk
     const int32_t* ir2 = (const int32_t*)(b->d_table + b->off_items[7][0]);
@@ -386,7 +398,8 @@ void enqueue_chunk_t(flb_batch* b, int c) {
       } else {
         const int ni = b->nitems[8];
         const int grid = b->o.workers > 0 ? std::max(1, std::min(ni, b->o.workers)) : ni;
-        k_batch_flat<2, T><<<grid, 256, 0, st>>>(reps, ir1, it1, ni, k);
+        if (b->flat_lg) k_batch_flat<2, T, kPlanLocalGauss><<<grid, 256, 0, st>>>(reps, ir1, it1, ni, k);
+        else k_batch_flat<2, T><<<grid, 256, 0, st>>>(reps, ir1, it1, ni, k);
       }
     }
   }
@@ -397,9 +410,15 @@ void enqueue_chunk_t(flb_batch* b, int c) {
       const int grid = b->o.workers > 0 ? std::max(1, std::min(ni, b->o.workers)) : ni;
       const int32_t* ir = (const int32_t*)(b->d_table + b->off_items[d][0]);
       const int32_t* it = (const int32_t*)(b->d_table + b->off_items[d][1]);
-      if (d == 4) k_batch_flat<1, T><<<grid, 256, 0, st>>>(reps, ir, it, ni, k);
-      else if (d == 5) k_batch_flat<2, T><<<grid, 256, 0, st>>>(reps, ir, it, ni, k);
-      else k_batch_flat<3, T><<<grid, 256, 0, st>>>(reps, ir, it, ni, k);
+      if (b->flat_lg) {
+        if (d == 4) k_batch_flat<1, T, kPlanLocalGauss><<<grid, 256, 0, st>>>(reps, ir, it, ni, k);
+        else if (d == 5) k_batch_flat<2, T, kPlanLocalGauss><<<grid, 256, 0, st>>>(reps, ir, it, ni, k);
+        else k_batch_flat<3, T, kPlanLocalGauss><<<grid, 256, 0, st>>>(reps, ir, it, ni, k);
+      } else {
+        if (d == 4) k_batch_flat<1, T><<<grid, 256, 0, st>>>(reps, ir, it, ni, k);
+        else if (d == 5) k_batch_flat<2, T><<<grid, 256, 0, st>>>(reps, ir, it, ni, k);
+        else k_batch_flat<3, T><<<grid, 256, 0, st>>>(reps, ir, it, ni, k);
+      }
     }
     for (int d = 1; d <= 3; ++d) {
       const int ni = b->nitems[d];
@@ -483,6 +502,8 @@ int flb_batch_create(const flb_batch_opts* opts, flb_batch** out) {
   b->nreps = 0;
   b->sub = o.item_rows ? o.item_rows / kBatchRY : 1;
   b->two_lg = false;
+  b->flat_lg = false;
+  b->lds_lg = false;
   for (int d = 0; d < 9; ++d) b->nitems[d] = 0;
   hipError_t e = hipGetDevice(&b->device);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, b->device);

@@ -262,17 +262,19 @@ struct Collide<1, T, NP> {
   static constexpr int Q = 3;
   __device__ __forceinline__ static void run(T (&f)[3], const KParams<T>& P, uint64_t site,
                                              uint32_t step) {
+    constexpr bool fixed = NP == kPlanLocalGauss;
+    const bool on = fixed || P.noise != kNoiseOff;
     // the variates depend on (site, step) only: drawn first, they overlap
     // the loads of f still in flight
     T z[4];
-    if (P.noise != kNoiseOff) draw4(P, site, step, 0u, z);
+    if (on) draw4<T, NP>(P, site, step, 0u, z);
     const double rho_d = density_sum(f);
     const T rho = (T)rho_d;
     const T Mj = P.a * (f[1] - f[2]);
     const T Ms = fma(P.c1, f[1] + f[2], -(P.c0 * f[0]));
     T xj = 0, xs = 0;
-    if (P.noise != kNoiseOff) {
-      const T sr = noise_scale(P, rho);
+    if (on) {
+      const T sr = fixed ? noise_scale_local(rho) : noise_scale(P, rho);
       xj = sr * P.sq_j * z[0];
       xs = sr * P.sq_s * z[1];
     }
@@ -338,10 +340,12 @@ struct Collide<3, T, NP> {
   static constexpr int Q = 7;
   __device__ __forceinline__ static void run(T (&f)[7], const KParams<T>& P, uint64_t site,
                                              uint32_t step) {
+    constexpr bool fixed = NP == kPlanLocalGauss;
+    const bool on = fixed || P.noise != kNoiseOff;
     T z[4], zz[4];
-    if (P.noise != kNoiseOff) {  // independent of f: overlaps its loads
-      draw4(P, site, step, 0u, z);
-      draw4(P, site, step, 1u, zz);
+    if (on) {  // independent of f: overlaps its loads
+      draw4<T, NP>(P, site, step, 0u, z);
+      draw4<T, NP>(P, site, step, 1u, zz);
     }
     const double rho_d = density_sum(f);
     const T rho = (T)rho_d;
@@ -353,8 +357,8 @@ struct Collide<3, T, NP> {
     const T Mn2 = P.e * ((sx + sy) - (T)2 * sz);
     const T Ms = fma(P.c1, (sx + sy) + sz, -(P.c0 * f[0]));
     T x[6] = {0, 0, 0, 0, 0, 0};
-    if (P.noise != kNoiseOff) {
-      const T sr = noise_scale(P, rho);
+    if (on) {
+      const T sr = fixed ? noise_scale_local(rho) : noise_scale(P, rho);
       const T gj = sr * P.sq_j, gn = sr * P.sq_n;
       x[0] = gj * z[0];
       x[1] = gj * z[1];

@@ -129,7 +129,7 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) {
   return xcd < r ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
 }
 
-template <int D, typename T, int RY, bool NT>
+template <int D, typename T, int RY, bool NT, int NP = kPlanRuntime>
 __device__ __forceinline__ void flat_tile(const T* __restrict__ g, T* __restrict__ h,
                                           const KParams<T>& P, uint32_t step, int64_t s0,
                                           uint32_t lane);
@@ -138,10 +138,12 @@ __device__ __forceinline__ void flat_tile(const T* __restrict__ g, T* __restrict
 // the dispatcher's round-robin XCD placement: an XCD-contiguous assignment
 // saved the halo re-fetches at tile edges (2.5 % of the reads) but measured
 // slower, the concurrently active tiles then spreading over 8 distant ranges.
-template <int D, typename T, int RY, bool NT>
+// NP: the noise plan (kPlanLocalGauss fixes local Gaussian noise at compile
+// time; the same arithmetic, so the same bits).
+template <int D, typename T, int RY, bool NT, int NP = kPlanRuntime>
 __global__ void __launch_bounds__(256) k_step_flat(const T* __restrict__ g, T* __restrict__ h,
                                                    KParams<T> P, uint32_t step) {
-  flat_tile<D, T, RY, NT>(g, h, P, step, (int64_t)blockIdx.x * 256 * RY, threadIdx.x);
+  flat_tile<D, T, RY, NT, NP>(g, h, P, step, (int64_t)blockIdx.x * 256 * RY, threadIdx.x);
 }
 
 // Element at a 32-bit byte offset from a block-uniform base pointer: the
@@ -158,6 +160,35 @@ __device__ __forceinline__ void st_at(T* __restrict__ base, uint32_t byte_off, T
     __builtin_nontemporal_store(v, p);
   else
     *p = v;
+}
+
+// Raw buffer access to a whole population array (Q planes of n values,
+// Q n S < 2^32 bytes): a per-lane byte offset plus a uniform byte offset
+// (plane and row) that stays in a scalar register, so the address needs no
+// vector arithmetic.  0x00020000: the resource word of the gfx9 family for
+// untyped 32-bit access.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+// NT: the non-temporal hint (cache-policy bit 1)
+template <bool NT>
+__device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, NT ? 2 : 0);
+}
+template <bool NT>
+__device__ __forceinline__ void buf_st(double v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, NT ? 2 : 0);
 }
 
 // Row step: a block covers blockDim.x consecutive x of RY consecutive rows
@@ -305,7 +336,7 @@ __device__ __forceinline__ FlatSite flat_site(const FlatOrigin& o, uint32_t s, u
 // row-major site order, so a lattice's sites fill every lane except in its
 // last tile.  Each lane derives (x, y, z) and its periodic neighbours
 // itself; all offsets are 32-bit byte offsets from the plane bases.
-template <int D, typename T, int RY, bool NT>
+template <int D, typename T, int RY, bool NT, int NP>
 __device__ __forceinline__ void flat_tile(const T* __restrict__ g, T* __restrict__ h,
                                           const KParams<T>& P, uint32_t step, int64_t s0,
                                           uint32_t lane) {
@@ -335,12 +366,14 @@ __device__ __forceinline__ void flat_tile(const T* __restrict__ g, T* __restrict
       }
     }
   }
+  // stores through a buffer resource: the plane offsets stay scalar
+  const __amdgpu_buffer_rsrc_t rh = buf_rsrc(h, (uint32_t)Q * n * S);
 #pragma unroll
   for (int j = 0; j < RY; ++j) {
     if (sj[j] < n) {
-      Collide<D, T>::run(f[j], P, (uint64_t)sj[j], step);
+      Collide<D, T, NP>::run(f[j], P, (uint64_t)sj[j], step);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) st_at<T, NT>(h + i * (int64_t)n, sj[j] * S, f[j][i]);
+      for (int i = 0; i < Q; ++i) buf_st<NT>(f[j][i], rh, sj[j] * S, (uint32_t)i * n * S);
     }
   }
 }
@@ -369,7 +402,7 @@ __device__ __forceinline__ int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1
 // One AA step of a flat tile in place on the single buffer a: from form
 // kFormAAC (even parity) to kFormAAS, or from kFormAAS to kFormAAC.  The
 // collisions are those of flat_tile on the same pre-collision values.
-template <int D, typename T, int RY, bool NT, int FORM>
+template <int D, typename T, int RY, bool NT, int FORM, int NP = kPlanRuntime>
 __device__ __forceinline__ void flat_tile_aa(T* a, const KParams<T>& P, uint32_t step, int64_t s0, uint32_t lane) {
   constexpr int Q = 2 * D + 1;
   constexpr uint32_t S = sizeof(T);
@@ -391,23 +424,24 @@ __device__ __forceinline__ void flat_tile_aa(T* a, const KParams<T>& P, uint32_t
       }
     }
   }
+  const __amdgpu_buffer_rsrc_t ra = buf_rsrc(a, (uint32_t)Q * n * S);
 #pragma unroll
   for (int j = 0; j < RY; ++j) {
     if (bj[j].s < n) {
-      Collide<D, T>::run(f[j], P, (uint64_t)bj[j].s, step);
+      Collide<D, T, NP>::run(f[j], P, (uint64_t)bj[j].s, step);
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
         // f_i* goes where opp(i) was read
         const int pl = FORM == kFormAAC ? opp(i) : i;
-        st_at<T, NT>(a + pl * (int64_t)n, aa_read_off<D>(bj[j], opp(i), FORM) * S, f[j][i]);
+        buf_st<NT>(f[j][i], ra, aa_read_off<D>(bj[j], opp(i), FORM) * S, (uint32_t)pl * n * S);
       }
     }
   }
 }
 
-template <int D, typename T, int RY, bool NT, int FORM>
+template <int D, typename T, int RY, bool NT, int FORM, int NP = kPlanRuntime>
 __global__ void __launch_bounds__(256) k_step_flat_aa(T* a, KParams<T> P, uint32_t step) {
-  flat_tile_aa<D, T, RY, NT, FORM>(a, P, step, (int64_t)blockIdx.x * 256 * RY, threadIdx.x);
+  flat_tile_aa<D, T, RY, NT, FORM, NP>(a, P, step, (int64_t)blockIdx.x * 256 * RY, threadIdx.x);
 }
 
 // Sum over the 64 lanes of a wave with DPP lane moves (no LDS): quad swaps,
@@ -508,6 +542,24 @@ __device__ __forceinline__ void step2_tile(const T* __restrict__ g, T* __restric
   T fs[TY + 2][Q];
   const bool own = lane < w;
   const uint32_t xo = x0 + (uint32_t)(own ? lane : 0);
+  // The owned columns' loads and stores go through buffer resources: the
+  // column offsets per lane, the plane and row offsets in scalar registers
+  // (3 % faster than 64-bit vector addresses; the halo columns, whose rows
+  // differ per lane, keep the loads of `first`)
+  const uint32_t nS = n * S;
+  const __amdgpu_buffer_rsrc_t rg = buf_rsrc(g, 5u * nS), rh = buf_rsrc(h, 5u * nS);
+  const uint32_t vx = xo * S, vxm = (xo == 0 ? nx - 1 : xo - 1) * S, vxp = (xo == nx - 1 ? 0 : xo + 1) * S;
+  auto first_buf = [&](uint32_t r, T (&f)[Q], double* rho) {
+    const uint32_t so = r * nx * S;
+    const uint32_t sm = (r == 0 ? ny - 1 : r - 1) * nx * S, sp = (r == ny - 1 ? 0 : r + 1) * nx * S;
+    f[0] = buf_ld<T>(rg, vx, so);
+    f[1] = buf_ld<T>(rg, vxm, nS + so);
+    f[2] = buf_ld<T>(rg, vxp, 2 * nS + so);
+    f[3] = buf_ld<T>(rg, vx, 3 * nS + sm);
+    f[4] = buf_ld<T>(rg, vx, 4 * nS + sp);
+    if (rho) *rho = density_sum(f);
+    Collide<2, T, NP>::run(f, P, (uint64_t)(r * nx + xo), step);
+  };
   double col = 0;
 #pragma unroll
   for (int k = 0; k < TY + 2; ++k) {
@@ -515,7 +567,13 @@ __device__ __forceinline__ void step2_tile(const T* __restrict__ g, T* __restric
     if (own && k <= hr + 1) {
       const int rr = (int)r0 - 1 + k;  // -1 .. r0 + hr
       const uint32_t r = rr < 0 ? (uint32_t)(rr + (int)ny) : ((uint32_t)rr >= ny ? (uint32_t)rr - ny : (uint32_t)rr);
-      first(xo, r, fs[k], (SAMPLE && k >= 1 && k <= hr) ? &rho : nullptr);
+      first_buf(r, fs[k], (SAMPLE && k >= 1 && k <= hr) ? &rho : nullptr);
+      // the x-moving populations of owned rows go to LDS at once: the lane
+      // keeps only f*_0, f*_3, f*_4 of its rows for the second step
+      if (k >= 1 && k <= hr) {
+        l1[k - 1][1 + lane] = fs[k][1];
+        l2[k - 1][1 + lane] = fs[k][2];
+      }
     }
     if constexpr (SAMPLE) {
       if (k >= 1 && k <= TY) {  // owned row k - 1: column sum in row order, row sum over the lanes
@@ -525,16 +583,10 @@ __device__ __forceinline__ void step2_tile(const T* __restrict__ g, T* __restric
       }
     }
   }
-  if (own) {
-    if constexpr (SAMPLE) colpart[(int64_t)ty * nx + xo] = col;
-#pragma unroll
-    for (int k = 0; k < TY; ++k) {
-      if (k < hr) {
-        l1[k][1 + lane] = fs[k + 1][1];
-        l2[k][1 + lane] = fs[k + 1][2];
-      }
-    }
+  if constexpr (SAMPLE) {
+    if (own) colpart[(int64_t)ty * nx + xo] = col;
   }
+
   if (lane < 2 * TY) {  // halo columns: lanes 0 .. TY-1 left (f*_1), TY .. 2TY-1 right (f*_2)
     const int k = lane < TY ? lane : lane - TY;
     if (k < hr) {
@@ -563,7 +615,7 @@ __device__ __forceinline__ void step2_tile(const T* __restrict__ g, T* __restric
       const uint32_t s = (r0 + (uint32_t)k) * nx + x;
       Collide<2, T, NP>::run(f, P, (uint64_t)s, step + 1u);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) st_at<T, NT>(h + i * (int64_t)n, s * S, f[i]);
+      for (int i = 0; i < Q; ++i) buf_st<NT>(f[i], rh, vx, (uint32_t)i * nS + (r0 + (uint32_t)k) * nx * S);
     }
   }
 }
