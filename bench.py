@@ -14,7 +14,9 @@ accumulated on the device; the FP64 lattice sums are taken at the end.
 The same line carries, each timed in this run with its oracle error:
 the one-step kernel on the same state (depth1), the plain and the tuned
 FP64 paths (the comparator), the D3Q7 512^3 FP32 lattice (c3_*) and the
-1024 + 256 replica FP32 ensemble (c4_*).  Prints one JSON line.
+1024 + 256 replica FP32 ensemble (c4_*); and the first 16 requests of the
+served stream under an HBM budget with two storage policies (c5_*).
+Prints one JSON line.
 """
 
 import argparse
@@ -423,6 +425,17 @@ def main():
         out["c3_err_vs_oracle"] = (c3.get("oracle") or {}).get("max_err")
         out["c4_err_vs_oracle_rho_ge_5"] = (c4.get("oracle") or {}).get("max_err_rho_ge_5")
 
+    if not args.no_legs:
+        log("served leg")
+        c5 = leg_served(torch, flb, args)
+        out["c5_served"] = c5
+        for pol in ("two", "auto"):
+            r = c5.get(pol) or {}
+            out[f"c5_{pol}_mlups"] = r.get("mlups")
+            out[f"c5_{pol}_p50_latency_s"] = r.get("p50_latency_s")
+            out[f"c5_{pol}_p99_latency_s"] = r.get("p99_latency_s")
+            out[f"c5_{pol}_mean_resident"] = r.get("mean_resident")
+
     if args.copy_probe_mib:
         nb = args.copy_probe_mib << 20
         src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
@@ -669,6 +682,26 @@ def leg_ensemble(torch, flb, inputs, tune, args, check=True):
     return out
 
 
+def leg_served(torch, flb, args, n=16, budget_gib=4.0):
+    """The served stream's first n requests (Poisson arrivals at 200/s,
+    D1Q3/D2Q5/D3Q7, sites log-U[1e3, 1e8], steps log-U[1e2, 1e5], FP32,
+    seed 0), served with an HBM budget of budget_gib under two storage
+    policies: two buffers for every request, and the adaptive one (one
+    buffer for D1Q3, two for D2Q5 and D3Q7 unless only the single-buffer
+    footprint fits the free budget).  Per policy: makespan, throughput,
+    p50/p99 latency and the requests resident at once."""
+    from paper_1606_07801_amd import serve
+    out = {"workload": f"served: first {n} requests of the Poisson(200/s) stream, seed 0, D1Q3/D2Q5/D3Q7, "
+                       f"sites log-U[1e3,1e8], steps log-U[1e2,1e5], fp32, HBM budget {budget_gib} GiB"}
+    for pol in ("two", "auto"):
+        reqs = serve.make_requests(n, 200.0, seed=0)
+        S = serve.Server(budget_bytes=int(budget_gib * 2 ** 30), layout=pol)
+        mk = S.run(reqs)
+        out[pol] = serve.summary(S, mk)
+        S.close()
+    return out
+
+
 def _timed(torch, fn, steps):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -877,6 +910,13 @@ def bench_served(torch, flb, inputs, tune, args):
     for frac in (0.5, 0.9):
         res, _ = run(frac * cap / mean_work)
         out[f"at_{frac}_of_capacity"] = res
+    # the same stream with a constrained budget under both storage policies
+    for pol in ("two", "auto"):
+        reqs = serve.make_requests(args.requests, 200.0, seed=0)
+        S = serve.Server(budget_bytes=8 << 30, layout=pol)
+        mk = S.run(reqs, progress=30.0)
+        out[f"budget_8gib_{pol}"] = serve.summary(S, mk)
+        S.close()
     if not args.no_cpu_baseline:
         out["oracle_check"] = served_oracle_check(serve, reqs)
     return out

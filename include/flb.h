@@ -55,7 +55,7 @@ enum {
   FLB_ENOMEM = -2,      /* buffer too small, or allocation failed */
   FLB_EDEVICE = -3,     /* HIP runtime error */
   FLB_ESTATE = -4,      /* call not valid in the handle's current state */
-  FLB_ENONFINITE = -5   /* non-finite populations detected (check mode) */
+  FLB_ENONFINITE = -5   /* non-finite populations detected (check mode, flb_set_check) */
 };
 
 enum { FLB_D1Q3 = 1, FLB_D2Q5 = 2, FLB_D3Q7 = 3 };
@@ -178,6 +178,13 @@ int flb_get_populations(flb_lattice* h, void* dst, int dst_on_device);
 /* Advance nsteps >= 0 time steps: eq. (LB) with eq. (collision) at every
  * site.  Asynchronous on the handle's stream. */
 int flb_step(flb_lattice* h, int64_t nsteps);
+
+/* Check mode (off by default): with every > 0, flb_step stops after each
+ * step t with t % every == 0 and after its last step, reads the state's
+ * lattice sums back (synchronising the stream) and, if any population is
+ * not finite, returns FLB_ENONFINITE with the lattice left at that step
+ * (flb_last_error names the step and the count).  every = 0 turns it off. */
+int flb_set_check(flb_lattice* h, int64_t every);
 
 /* Steps completed so far. */
 int flb_get_step(flb_lattice* h, int64_t* step);

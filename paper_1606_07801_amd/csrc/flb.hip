@@ -789,6 +789,19 @@ int upload_k(flb_lattice* h, const int32_t* kvec, int nk, int set) {
   return FLB_OK;
 }
 
+// Check mode: the non-finite count of the lattice sums of the current
+// state (synchronises); FLB_ENONFINITE when there are any.
+int check_finite(flb_lattice* h) {
+  launch_moments(h);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(h->stage->red, h->work + h->wl.red_out, sizeof(double) * kNV, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  const int64_t bad = (int64_t)h->stage->red[kNV - 1];
+  if (bad > 0)
+    return fail(FLB_ENONFINITE, "%lld non-finite populations after step %lld", (long long)bad, (long long)h->step);
+  return FLB_OK;
+}
+
 struct DeviceGuard {
   int prev = -1;
   explicit DeviceGuard(int dev) {
@@ -832,6 +845,9 @@ int scratch_for(int dev, void** out) {
 }
 
 }  // namespace
+
+// the step loop of flb_step (defined with the exported functions)
+static int step_unchecked(flb_lattice* h, int64_t nsteps);
 
 // ---------------------------------------------------------------------------
 // exported functions
@@ -959,6 +975,7 @@ int flb_create(const flb_params* p, void* d_pop, size_t pop_bytes, void* d_work,
   h->corr_every = 0;
   h->corr_nk = h->corr_nlag = h->corr_nsb = 0;
   h->corr_count = 0;
+  h->check_every = 0;
   h->corr_mem = nullptr;
   h->prof_mem = nullptr;
   h->reg_n = 0;
@@ -1068,6 +1085,29 @@ int flb_step(flb_lattice* h, int64_t nsteps) {
   if (nsteps < 0) return fail(FLB_EINVAL, "nsteps must be >= 0");
   if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
   DeviceGuard g(h->device);
+  if (h->check_every <= 0 || nsteps == 0) return step_unchecked(h, nsteps);
+  // check mode: run up to each multiple of check_every, check, go on
+  const int64_t end = h->step + nsteps;
+  while (h->step < end) {
+    const int64_t next = std::min(end, (h->step / h->check_every + 1) * h->check_every);
+    int rc = step_unchecked(h, next - h->step);
+    if (rc) return rc;
+    rc = check_finite(h);
+    if (rc) return rc;
+  }
+  return FLB_OK;
+}
+
+int flb_set_check(flb_lattice* h, int64_t every) {
+  if (!h) return fail(FLB_EINVAL, "NULL handle");
+  if (every < 0) return fail(FLB_EINVAL, "every must be >= 0");
+  h->check_every = every;
+  return FLB_OK;
+}
+
+}  // extern "C"
+
+static int step_unchecked(flb_lattice* h, int64_t nsteps) {
   size_t lds = 0;
   int corr_lds = 0;
   if (h->resident && h->reg_n == 0 && resident_lds(h, &lds, &corr_lds)) {
@@ -1126,6 +1166,8 @@ int flb_step(flb_lattice* h, int64_t nsteps) {
   HIP_TRY(hipGetLastError());
   return FLB_OK;
 }
+
+extern "C" {
 
 int flb_get_step(flb_lattice* h, int64_t* step) {
   if (!h || !step) return fail(FLB_EINVAL, "NULL argument");

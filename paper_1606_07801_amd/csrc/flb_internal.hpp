@@ -78,6 +78,7 @@ struct flb_lattice {
   int64_t corr_every;    // > 0: sample every this many steps
   int corr_nk, corr_nlag, corr_nsb;
   int64_t corr_count;    // samples accumulated
+  int64_t check_every;   // > 0: flb_step checks the state for non-finite values
   char* corr_mem;
   size_t corr_off[7];
   // small lattices: one workgroup steps the whole lattice in LDS

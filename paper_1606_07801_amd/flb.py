@@ -25,7 +25,7 @@ SK_SNAPSHOT, SK_SAMPLE, SK_READ, SK_RESET = 0, 1, 2, 3
 # exported symbols, in the order include/flb.h declares them
 EXPORTS = (
     "flb_version", "flb_last_error", "flb_lattice_constants", "flb_required_bytes",
-    "flb_create", "flb_set_populations", "flb_get_populations", "flb_step",
+    "flb_create", "flb_set_populations", "flb_get_populations", "flb_step", "flb_set_check",
     "flb_get_step", "flb_moments", "flb_structure_factor", "flb_set_sampling",
     "flb_set_moment_sampling", "flb_sampled_moments", "flb_set_correlation",
     "flb_correlation", "flb_fourier_amplitudes", "flb_profile", "flb_set_regions", "flb_profile_noalloc",
@@ -103,6 +103,7 @@ def load(path=LIB_PATH):
         "flb_set_populations": ([vp, vp, ctypes.c_int, i64], ctypes.c_int),
         "flb_get_populations": ([vp, vp, ctypes.c_int], ctypes.c_int),
         "flb_step": ([vp, i64], ctypes.c_int),
+        "flb_set_check": ([vp, i64], ctypes.c_int),
         "flb_get_step": ([vp, ctypes.POINTER(i64)], ctypes.c_int),
         "flb_moments": ([vp, ctypes.POINTER(Moments)], ctypes.c_int),
         "flb_structure_factor": ([vp, vp, i32, i32, dp], ctypes.c_int),
@@ -254,6 +255,11 @@ class Lattice:
 
     def step(self, n=1):
         check(load().flb_step(self.handle, int(n)))
+
+    def set_check(self, every):
+        """Check mode: flb_step checks for non-finite populations every
+        `every` steps and at the end of each call (FLB_ENONFINITE); 0 = off."""
+        check(load().flb_set_check(self.handle, int(every)))
 
     @property
     def t(self):

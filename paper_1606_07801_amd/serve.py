@@ -28,7 +28,8 @@ from . import flb, inputs
 
 class Request:
     __slots__ = ("id", "arrival", "d", "dims", "steps", "omega", "rho", "seed", "precision",
-                 "lat", "bytes", "start", "done", "remaining", "result", "error", "keep_state", "layout")
+                 "lat", "bytes", "start", "done", "remaining", "result", "error", "keep_state", "layout",
+                 "alt_bytes")
 
     def __init__(self, rid, arrival, d, dims, steps, omega, rho, seed, precision=4, keep_state=False):
         self.id, self.arrival, self.d, self.dims = rid, float(arrival), int(d), tuple(int(x) for x in dims)
@@ -42,6 +43,7 @@ class Request:
         self.error = None
         self.keep_state = keep_state
         self.layout = "two"
+        self.alt_bytes = None
 
     @property
     def sites(self):
@@ -60,18 +62,37 @@ def request_bytes(req):
     return pop + work + 512
 
 
+def aa_eligible(req):
+    """The AA layout steps with the flat kernel, which needs Q N precision < 2^32."""
+    return req.sites * (2 * req.d + 1) * req.precision < (1 << 32)
+
+
 def pick_layout(req, policy):
-    """Storage layout of a request.  "two": two buffers for every request;
-    "aa": one buffer (AA layout, half the population memory) for every
-    request; "auto": one buffer except for D2Q5 lattices the two-step pass
-    can take (their two buffers buy a pass per two steps), so the models
-    that step one pass per step anyway hold half the memory."""
-    if policy == "two":
+    """Preferred storage layout of a request.  "two": two buffers for every
+    request; "aa": one buffer (AA layout, half the population memory) for
+    every request that can take it; "auto": the faster layout per model --
+    one buffer for D1Q3 (as fast or faster), two for D2Q5 (a two-step pass
+    per two steps) and D3Q7 (its in-place steps run 10 % slower) -- with the
+    single buffer as a fallback under memory pressure (fallback_bytes)."""
+    if policy == "two" or not aa_eligible(req):
         return "two"
-    if policy == "aa":
-        return "aa" if req.sites * (2 * req.d + 1) * req.precision < (1 << 32) else "two"
-    two_step = req.d == 2 and req.sites * 5 * req.precision < (1 << 32)
-    return "two" if two_step or req.sites * (2 * req.d + 1) * req.precision >= (1 << 32) else "aa"
+    if policy == "aa" or req.d == 1:
+        return "aa"
+    return "two"
+
+
+def fallback_bytes(req, policy):
+    """Device bytes of the request in the AA layout when policy "auto" may
+    admit it that way because its preferred two-buffer footprint does not fit
+    the free budget (None when there is no such fallback)."""
+    if policy != "auto" or req.layout != "two" or not aa_eligible(req):
+        return None
+    keep = req.layout
+    req.layout = "aa"
+    try:
+        return request_bytes(req)
+    finally:
+        req.layout = keep
 
 
 def initial_state(torch, req, device):
@@ -131,13 +152,15 @@ class Server:
         self.ticks = 0
         self.site_updates = 0
         self.layout = layout
+        self.fallbacks = 0         # requests admitted in the AA layout under memory pressure
         self.peak_active = 0
         self.active_ticks = 0      # sum over ticks of the number of active requests
 
     def submit(self, req):
         req.layout = pick_layout(req, self.layout)
         req.bytes = request_bytes(req)
-        if req.bytes > self.budget:
+        req.alt_bytes = fallback_bytes(req, self.layout)
+        if min(req.bytes, req.alt_bytes or req.bytes) > self.budget:
             req.error = f"needs {req.bytes} bytes, budget is {self.budget}"
             self.rejected.append(req)
             return False
@@ -145,8 +168,16 @@ class Server:
         return True
 
     def _admit(self, now):
-        while self.queue and self.queue[0].bytes <= self.budget - self.used:
-            req = self.queue.popleft()
+        while self.queue:
+            req = self.queue[0]
+            free = self.budget - self.used
+            if req.bytes > free:
+                # the single-buffer footprint, when the preferred one does not fit
+                if req.alt_bytes is None or req.alt_bytes > free:
+                    break
+                req.layout, req.bytes = "aa", req.alt_bytes
+                self.fallbacks += 1
+            self.queue.popleft()
             start_request(self.torch, req, self.device)
             self.used += req.bytes
             req.start = now
@@ -222,7 +253,8 @@ def summary(server, makespan):
         "p50_latency_s": round(float(np.percentile(lat, 50)), 4) if len(lat) else None,
         "p99_latency_s": round(float(np.percentile(lat, 99)), 4) if len(lat) else None,
         "mlups": round(ups / makespan / 1e6, 1) if makespan > 0 else None,
-        "ticks": server.ticks, "layout": server.layout, "peak_resident": server.peak_active,
+        "ticks": server.ticks, "layout": server.layout, "aa_fallbacks": server.fallbacks,
+        "peak_resident": server.peak_active,
         "mean_resident": round(server.active_ticks / server.ticks, 2) if server.ticks else 0,
         "budget_gb": round(server.budget / 2 ** 30, 2),
     }

@@ -170,3 +170,32 @@ def test_errors_from_device_calls():
         L.structure_factor(None, mode="read")
     assert e.value.code == flb.FLB_ESTATE
     L.close()
+
+
+@pytest.mark.parametrize("kernel,dims", [("two", (300, 70)), ("auto", (60, 40)), ("flat", (1000,))])
+def test_check_mode_reports_nonfinite(kernel, dims):
+    # a NaN set through flb_set_populations: with checks every step the next
+    # step stops with FLB_ENONFINITE at step 1; every 4 steps, at step 4
+    d = len(dims)
+    f0 = poisson_state(d, dims, 10.0, seed=3).astype(np.float32)
+    for every, stop in ((1, 1), (4, 4)):
+        bad = f0.copy()
+        bad.reshape(-1)[123] = np.nan
+        L = gpu_lattice(d, dims, 4, kernel=kernel)
+        L.set_populations(bad)
+        L.set_check(every)
+        with pytest.raises(flb.FlbError) as e:
+            L.step(10)
+        assert e.value.code == flb.FLB_ENONFINITE and L.t == stop, (every, L.t)
+        L.close()
+    # a finite state passes the checks, with results equal to unchecked steps
+    A = gpu_lattice(d, dims, 4, kernel=kernel)
+    B = gpu_lattice(d, dims, 4, kernel=kernel)
+    for L in (A, B):
+        L.set_populations(f0)
+    A.set_check(3)
+    A.step(10)
+    B.step(10)
+    assert A.t == 10 and np.array_equal(A.get_populations(), B.get_populations())
+    A.close()
+    B.close()
