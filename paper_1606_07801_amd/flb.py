@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "lib", "libflb.so")
+# FLB_LIB selects another build of the library (the sanitized one, for instance)
+LIB_PATH = os.environ.get("FLB_LIB") or os.path.join(HERE, "lib", "libflb.so")
 
 FLB_OK, FLB_EINVAL, FLB_ENOMEM, FLB_EDEVICE, FLB_ESTATE, FLB_ENONFINITE = 0, -1, -2, -3, -4, -5
 MODELS = {"D1Q3": 1, "D2Q5": 2, "D3Q7": 3, 1: 1, 2: 2, 3: 3}
