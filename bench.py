@@ -173,7 +173,7 @@ def kernel_name(cfg, d=2, prec="float"):
             return f"flb::k_step2_d3<{prec}, {nt}, 1>"
         return f"flb::k_step2_d2<{prec}, {2 if ty <= 2 else ty}, {nt}, false, 1>"
     if cfg.get("kernel") == "flat":
-        return f"flb::k_step_flat<{d}, {prec}, {cfg.get('tile_rows') or (2 if d == 2 else 1)}, {nt}>"
+        return f"flb::k_step_flat<{d}, {prec}, {cfg.get('tile_rows') or (2 if d == 2 else 1)}, {nt}, 1>"
     if cfg.get("kernel") == "plain":
         return f"flb::k_step_plain<{d}, {prec}>"
     return f"flb::k_step_rows<{d}, {prec}, {cfg.get('tile_rows') or 4}, {nt}>"
@@ -654,7 +654,7 @@ def leg_ensemble(torch, flb, inputs, tune, args, check=True):
     # counted bytes and VALU cycles of one step: per chunk of c steps the
     # LDS kernel runs once, the two-step kernel c/2 times, the advance once
     c = bcfg["chunk"]
-    per_step = {"flb::k_batch_two<float, %d, 1>" % bcfg["width"]: 0.5, "flb::k_batch_lds_d1<float, 16>": 1.0 / c,
+    per_step = {"flb::k_batch_two<float, %d, 1>" % bcfg["width"]: 0.5, "flb::k_batch_lds_d1<float, 16, 1>": 1.0 / c,
                 "flb::k_batch_advance<float>": 1.0 / c}
     tb = va = 0.0
     have = True

@@ -19,8 +19,8 @@ def test_parse_defaults(monkeypatch):
 
 def test_kernel_names():
     assert bench.kernel_name({"kernel": "two", "tile_rows": 8, "nt_store": 1}) == "flb::k_step2_d2<float, 8, true, false, 1>"
-    assert bench.kernel_name({"kernel": "flat", "tile_rows": 2, "nt_store": 1}) == "flb::k_step_flat<2, float, 2, true>"
-    assert bench.kernel_name({"kernel": "flat", "tile_rows": 1, "nt_store": 1}, d=3) == "flb::k_step_flat<3, float, 1, true>"
+    assert bench.kernel_name({"kernel": "flat", "tile_rows": 2, "nt_store": 1}) == "flb::k_step_flat<2, float, 2, true, 1>"
+    assert bench.kernel_name({"kernel": "flat", "tile_rows": 1, "nt_store": 1}, d=3) == "flb::k_step_flat<3, float, 1, true, 1>"
     assert bench.kernel_name({"kernel": "plain"}, prec="double") == "flb::k_step_plain<2, double>"
     assert bench.steps_per_launch({"kernel": "two"}) == 2 and bench.steps_per_launch({"kernel": "flat"}) == 1
 
