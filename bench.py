@@ -154,6 +154,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-legs", action="store_true", help="skip the D3Q7 and ensemble legs")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle checks of the legs")
+    ap.add_argument("--no-served", action="store_true", help="skip the served leg")
     ap.add_argument("--requests", type=int, default=48, help="served workload: number of requests")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -425,7 +426,7 @@ def main():
         out["c3_err_vs_oracle"] = (c3.get("oracle") or {}).get("max_err")
         out["c4_err_vs_oracle_rho_ge_5"] = (c4.get("oracle") or {}).get("max_err_rho_ge_5")
 
-    if not args.no_legs:
+    if not args.no_legs and not args.no_served:
         log("served leg")
         c5 = leg_served(torch, flb, args)
         out["c5_served"] = c5
