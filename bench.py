@@ -170,8 +170,6 @@ def kernel_name(cfg, d=2, prec="float"):
     nt = "true" if cfg.get("nt_store") else "false"
     if cfg.get("kernel") == "two":
         ty = cfg.get("tile_rows") or 8
-        if d == 3:
-            return f"flb::k_step2_d3<{prec}, {nt}, 1>"
         return f"flb::k_step2_d2<{prec}, {2 if ty <= 2 else ty}, {nt}, false, 1>"
     if cfg.get("kernel") == "flat":
         return f"flb::k_step_flat<{d}, {prec}, {cfg.get('tile_rows') or (2 if d == 2 else 1)}, {nt}, 1>"
@@ -610,9 +608,12 @@ def _check_members(flb, B, lats, reps, kept, steps):
                      "max_err_well_conditioned": float(err[ok].max()) if ok.any() else None,
                      "sites_near_rho0": int((minrho <= NEAR_ZERO[4]).sum())})
     hi = [row["max_err"] for row in rows if row["rho"] >= 5.0]
-    lo = [row for row in rows if row["rho"] < 5.0]
+    # members below rho 5 whose every site saw a near-zero collision have no
+    # well-conditioned sites and contribute nothing here
+    lo = [row["max_err_well_conditioned"] for row in rows
+          if row["rho"] < 5.0 and row["max_err_well_conditioned"] is not None]
     return {"steps": steps, "members": rows, "max_err_rho_ge_5": max(hi) if hi else None,
-            "max_err_rho_lt_5_well_conditioned": max((row["max_err_well_conditioned"] or 0.0) for row in lo) if lo else None}
+            "max_err_rho_lt_5_well_conditioned": max(lo) if lo else None}
 
 
 def leg_ensemble(torch, flb, inputs, tune, args, check=True):
