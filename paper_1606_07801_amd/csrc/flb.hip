@@ -116,19 +116,22 @@ KParams<T> make_kparams(const flb_params& p, double rho_eq) {
   k.ny = p.n[1];
   k.nz = p.n[2];
   k.n = p.n[0] * p.n[1] * p.n[2];
-  k.a = (T)(1.0 / std::sqrt(th));
-  k.b = (T)(1.0 / std::sqrt(2.0 * th));
-  k.e = (T)(1.0 / std::sqrt(6.0 * th));
-  k.c0 = (T)std::sqrt(d * th / (1.0 - d * th));
-  k.c1 = (T)std::sqrt((1.0 - d * th) / (d * th));
-  k.w1 = (T)(th / 2.0);
-  k.om_j = (T)oj;
-  k.om_n = (T)on;
-  k.om_s = (T)os;
-  k.sq_j = (T)(law * std::sqrt(oj * (2.0 - oj)));
-  k.sq_n = (T)(law * std::sqrt(on * (2.0 - on)));
-  k.sq_s = (T)(law * std::sqrt(os * (2.0 - os)));
   k.rho_eq = (T)rho_eq;
+  // folded products of the collision (in double, rounded once)
+  const double a = 1.0 / std::sqrt(th), b = 1.0 / std::sqrt(2.0 * th), e = 1.0 / std::sqrt(6.0 * th);
+  const double c0 = std::sqrt(d * th / (1.0 - d * th)), c1 = std::sqrt((1.0 - d * th) / (d * th));
+  const double w1 = th / 2.0;
+  const double sj = law * std::sqrt(oj * (2.0 - oj)), sn = law * std::sqrt(on * (2.0 - on));
+  const double ss = law * std::sqrt(os * (2.0 - os));
+  k.nA = (T)(w1 * a * sj);
+  k.nB = (T)(w1 * b * sn);
+  k.nC = (T)(w1 * c1 * ss);
+  k.nE = (T)(w1 * e * sn);
+  k.kj = (T)(w1 * a * a * oj);
+  k.kn = (T)(w1 * b * b * on);
+  k.ke = (T)(w1 * e * e * on);
+  k.ks = (T)(w1 * c1 * c1 * os);
+  k.ks0 = (T)(w1 * c1 * c0 * os);
   k.k0 = (uint32_t)(p.seed & 0xFFFFFFFFull);
   k.k1 = (uint32_t)(p.seed >> 32);
   k.noise = p.noise;

@@ -42,14 +42,16 @@ enum NoisePlan : int { kPlanRuntime = 0, kPlanLocalGauss = 1 };
 template <typename T>
 struct KParams {
   int64_t nx, ny, nz, n;   // box and site count
-  T a;                     // 1/sqrt(theta)           current moments
-  T b;                     // 1/sqrt(2 theta)         first traceless moment
-  T e;                     // 1/sqrt(6 theta)         second traceless moment (D3Q7)
-  T c0, c1;                // trace moment: m^s_0 = -c0, m^s_i = c1
-  T w1;                    // theta / 2, weight of every moving population
-  T om_j, om_n, om_s;      // relaxation rates per class
-  T sq_j, sq_n, sq_s;      // sqrt(omega (2 - omega)) per class, times sqrt(3) for the flat law
   T rho_eq;                // density of the global noise mode
+  // The collision's constants, folded with the back-transform weight
+  // w1 = theta/2 of the moving populations.  Basis scales (Sec. II):
+  // a = 1/sqrt(theta) (currents), b = 1/sqrt(2 theta) and e = 1/sqrt(6 theta)
+  // (traceless moments), c1 = sqrt((1 - d theta)/(d theta)) on the moving
+  // populations and -c0 = -sqrt(d theta/(1 - d theta)) on f_0 (trace).
+  // Rates om per class (j: currents, n: traceless, s: trace) and noise
+  // factors sq = sqrt(om (2 - om)) (times sqrt(3) for the flat law).
+  T nA, nB, nC, nE;        // noise scales w1 a sq_j, w1 b sq_n, w1 c1 sq_s, w1 e sq_n
+  T kj, kn, ke, ks, ks0;   // w1 a^2 om_j, w1 b^2 om_n, w1 e^2 om_n, w1 c1^2 om_s, w1 c1 c0 om_s
   uint32_t k0, k1;         // Philox key (seed low / high word)
   int32_t noise;           // NoiseMode
   int32_t law;             // NoiseLaw
@@ -205,6 +207,73 @@ __device__ __forceinline__ void draw4(const KParams<T>& P, uint64_t site, uint32
   }
 }
 
+// Noise terms of one Philox block for the collision: X_k = S_k sqrt(rn) z_k
+// with z_k the block's k-th unit variate (Gaussian: z_0, z_1 from the pair
+// (c0, c1) as cos and sin, z_2, z_3 from (c2, c3); flat: 2 u_k - 1), S_k the
+// folded scale of the moment that takes it and rn the density of the noise
+// amplitude.  c holds the block's Philox output words.
+//
+// Float, Gaussian law: the amplitude enters the Box-Muller radius,
+// sqrt(rn) sqrt(-2 ln u0) = sqrt(rn (-2 ln 2) log2 u0), one root per pair
+// instead of two roots and a product (the same value up to rounding).
+__device__ __forceinline__ void scaled_pair(uint32_t r0, uint32_t r1, float rk, float Sa, float Sb,
+                                            float& Xa, float& Xb) {
+  const float u0 = word_to_uniform<float>(r0), u1 = word_to_uniform<float>(r1);
+  const float R = __builtin_amdgcn_sqrtf(rk * __builtin_amdgcn_logf(u0));  // rk = -2 ln 2 rn
+  Xa = (Sa * R) * __builtin_amdgcn_cosf(u1);
+  Xb = (Sb * R) * __builtin_amdgcn_sinf(u1);
+}
+__device__ __forceinline__ void scaled_pair(uint32_t r0, uint32_t r1, double sr, double Sa, double Sb,
+                                            double& Xa, double& Xb) {
+  double z0, z1;
+  gauss_pair(r0, r1, z0, z1);  // sr = sqrt(rn)
+  Xa = (Sa * sr) * z0;
+  Xb = (Sb * sr) * z1;
+}
+__device__ __forceinline__ float amp_root(float rn) { return __builtin_amdgcn_sqrtf(rn); }
+__device__ __forceinline__ double amp_root(double rn) { return sqrt(rn); }
+
+template <typename T, int NP = kPlanRuntime>
+__device__ __forceinline__ void noise_terms(const KParams<T>& P, const uint32_t (&c)[4], T rn, T Sa, T Sb,
+                                            T Sc, T Sd, T (&X)[4]) {
+  if (NP == kPlanLocalGauss || P.law == kLawGauss) {
+    if constexpr (sizeof(T) == 4) {
+      const T rk = rn * (T)-1.38629436111989061;  // -2 ln 2
+      scaled_pair(c[0], c[1], rk, Sa, Sb, X[0], X[1]);
+      scaled_pair(c[2], c[3], rk, Sc, Sd, X[2], X[3]);
+    } else {
+      const T sr = amp_root(rn);
+      scaled_pair(c[0], c[1], sr, Sa, Sb, X[0], X[1]);
+      scaled_pair(c[2], c[3], sr, Sc, Sd, X[2], X[3]);
+    }
+  } else {  // flat law on (-1, 1); the sqrt(3) lives in the scales
+    const T sr = amp_root(rn);
+    X[0] = (Sa * sr) * ((T)2 * word_to_uniform<T>(c[0]) - (T)1);
+    X[1] = (Sb * sr) * ((T)2 * word_to_uniform<T>(c[1]) - (T)1);
+    X[2] = (Sc * sr) * ((T)2 * word_to_uniform<T>(c[2]) - (T)1);
+    X[3] = (Sd * sr) * ((T)2 * word_to_uniform<T>(c[3]) - (T)1);
+  }
+}
+
+// Philox output words of block `block` at (site, step).
+template <typename T>
+__device__ __forceinline__ void noise_words(const KParams<T>& P, uint64_t site, uint32_t step, uint32_t block,
+                                            uint32_t (&c)[4]) {
+  c[0] = (uint32_t)site;
+  c[1] = (uint32_t)(site >> 32);
+  c[2] = step;
+  c[3] = block;
+  philox4x32_10(c[0], c[1], c[2], c[3], P.k0, P.k1);
+}
+
+// Density of the noise amplitude: the local density clamped at zero, or the
+// global mean density.
+template <typename T, int NP>
+__device__ __forceinline__ T noise_density(const KParams<T>& P, T rho) {
+  if (NP == kPlanLocalGauss || P.noise == kNoiseLocal) return rho > (T)0 ? rho : (T)0;
+  return P.rho_eq;
+}
+
 // Site density sum_i f_i in index order, in double.  For float populations
 // this is the correctly rounded sum of the stored values, so that the clamp
 // at zero of the noise amplitude (where sqrt(rho) is not Lipschitz) is
@@ -236,20 +305,6 @@ __device__ __forceinline__ double rest_of(double rho, const double (&fi)[N]) {
   return rho - s;
 }
 
-__device__ __forceinline__ double noise_scale(const KParams<double>& P, double rho) {
-  const double rn = P.noise == kNoiseLocal ? (rho > 0.0 ? rho : 0.0) : P.rho_eq;
-  return sqrt(rn);
-}
-__device__ __forceinline__ float noise_scale(const KParams<float>& P, float rho) {
-  const float rn = P.noise == kNoiseLocal ? (rho > 0.0f ? rho : 0.0f) : P.rho_eq;
-  return __builtin_amdgcn_sqrtf(rn);
-}
-// the same for local noise known at compile time
-__device__ __forceinline__ double noise_scale_local(double rho) { return sqrt(rho > 0.0 ? rho : 0.0); }
-__device__ __forceinline__ float noise_scale_local(float rho) {
-  return __builtin_amdgcn_sqrtf(rho > 0.0f ? rho : 0.0f);
-}
-
 // ---------------------------------------------------------------------------
 // Per-site collision.  f holds the pre-collision populations of one site in
 // the velocity order 0, +x, -x, +y, -y, +z, -z and is overwritten with the
@@ -257,6 +312,14 @@ __device__ __forceinline__ float noise_scale_local(float rho) {
 template <int D, typename T, int NP = kPlanRuntime>
 struct Collide;
 
+// In every model the moving populations change by
+//   f_i* = f_i + w1 sum_{a >= 1} m_i^a (xi^a - om_a M^a),
+// written with the folded products of KParams.  A moment M^a = m S^a, with
+// m its basis scale (a, b, e or c1) and S^a an integer combination of the
+// moving populations (f_1 - f_2, f_1 + f_2 - f_3 - f_4, ...), contributes
+// w1 m (xi^a - om_a M^a) = X^a - k_a S^a with k_a = w1 m^2 om_a and X^a its
+// noise term (noise_terms); the trace moment's entry -c0 on f_0 adds
+// ks0 f_0.  The rest population takes the residual (rest_of).
 template <typename T, int NP>
 struct Collide<1, T, NP> {
   static constexpr int Q = 3;
@@ -264,25 +327,19 @@ struct Collide<1, T, NP> {
                                              uint32_t step) {
     constexpr bool fixed = NP == kPlanLocalGauss;
     const bool on = fixed || P.noise != kNoiseOff;
-    // the variates depend on (site, step) only: drawn first, they overlap
-    // the loads of f still in flight
-    T z[4];
-    if (on) draw4<T, NP>(P, site, step, 0u, z);
+    // the words depend on (site, step) only: drawn first, they overlap the
+    // loads of f still in flight
+    uint32_t c[4];
+    if (on) noise_words(P, site, step, 0u, c);
     const double rho_d = density_sum(f);
     const T rho = (T)rho_d;
-    const T Mj = P.a * (f[1] - f[2]);
-    const T Ms = fma(P.c1, f[1] + f[2], -(P.c0 * f[0]));
-    T xj = 0, xs = 0;
-    if (on) {
-      const T sr = fixed ? noise_scale_local(rho) : noise_scale(P, rho);
-      xj = sr * P.sq_j * z[0];
-      xs = sr * P.sq_s * z[1];
-    }
-    const T dj = fma(-P.om_j, Mj, xj);
-    const T ds = fma(-P.om_s, Ms, xs);
-    const T cj = P.a * dj, cs = P.c1 * ds;
-    const T f1 = fma(P.w1, cs + cj, f[1]);
-    const T f2 = fma(P.w1, cs - cj, f[2]);
+    T X[4] = {0, 0, 0, 0};
+    if (on) noise_terms<T, NP>(P, c, noise_density<T, NP>(P, rho), P.nA, P.nC, P.nC, P.nC, X);
+    // current (j) and trace (s) moments
+    const T Cj = fma(-P.kj, f[1] - f[2], X[0]);
+    const T Cs = fma(-P.ks, f[1] + f[2], fma(P.ks0, f[0], X[1]));
+    const T f1 = f[1] + (Cs + Cj);
+    const T f2 = f[2] + (Cs - Cj);
     f[1] = f1;
     f[2] = f2;
     const T mv[2] = {f1, f2};
@@ -297,35 +354,22 @@ struct Collide<2, T, NP> {
                                              uint32_t step) {
     constexpr bool fixed = NP == kPlanLocalGauss;
     const bool on = fixed || P.noise != kNoiseOff;
-    T z[4];
-    if (on) draw4<T, NP>(P, site, step, 0u, z);  // independent of f: overlaps its loads
+    uint32_t c[4];
+    if (on) noise_words(P, site, step, 0u, c);  // independent of f: overlaps its loads
     const double rho_d = density_sum(f);
     const T rho = (T)rho_d;
+    T X[4] = {0, 0, 0, 0};
+    if (on) noise_terms<T, NP>(P, c, noise_density<T, NP>(P, rho), P.nA, P.nA, P.nB, P.nC, X);
     const T sx = f[1] + f[2], sy = f[3] + f[4];
-    const T Mx = P.a * (f[1] - f[2]);
-    const T My = P.a * (f[3] - f[4]);
-    const T Mn = P.b * (sx - sy);
-    const T Ms = fma(P.c1, sx + sy, -(P.c0 * f[0]));
-    T x1 = 0, x2 = 0, x3 = 0, x4 = 0;
-    if (on) {
-      const T sr = fixed ? noise_scale_local(rho) : noise_scale(P, rho);
-      const T gj = sr * P.sq_j;
-      x1 = gj * z[0];
-      x2 = gj * z[1];
-      x3 = sr * P.sq_n * z[2];
-      x4 = sr * P.sq_s * z[3];
-    }
-    const T dx = fma(-P.om_j, Mx, x1);
-    const T dy = fma(-P.om_j, My, x2);
-    const T dn = fma(-P.om_n, Mn, x3);
-    const T ds = fma(-P.om_s, Ms, x4);
-    const T cx = P.a * dx, cy = P.a * dy;
-    const T pn = P.b * dn, ps = P.c1 * ds;
-    const T hx = pn + ps, hy = ps - pn;
-    const T f1 = fma(P.w1, hx + cx, f[1]);
-    const T f2 = fma(P.w1, hx - cx, f[2]);
-    const T f3 = fma(P.w1, hy + cy, f[3]);
-    const T f4 = fma(P.w1, hy - cy, f[4]);
+    const T Cx = fma(-P.kj, f[1] - f[2], X[0]);                // currents
+    const T Cy = fma(-P.kj, f[3] - f[4], X[1]);
+    const T Pn = fma(-P.kn, sx - sy, X[2]);                    // traceless
+    const T Ps = fma(-P.ks, sx + sy, fma(P.ks0, f[0], X[3]));  // trace
+    const T Hx = Pn + Ps, Hy = Ps - Pn;
+    const T f1 = f[1] + (Hx + Cx);
+    const T f2 = f[2] + (Hx - Cx);
+    const T f3 = f[3] + (Hy + Cy);
+    const T f4 = f[4] + (Hy - Cy);
     f[1] = f1;
     f[2] = f2;
     f[3] = f3;
@@ -342,48 +386,35 @@ struct Collide<3, T, NP> {
                                              uint32_t step) {
     constexpr bool fixed = NP == kPlanLocalGauss;
     const bool on = fixed || P.noise != kNoiseOff;
-    T z[4], zz[4];
+    uint32_t c[4], cc[4];
     if (on) {  // independent of f: overlaps its loads
-      draw4<T, NP>(P, site, step, 0u, z);
-      draw4<T, NP>(P, site, step, 1u, zz);
+      noise_words(P, site, step, 0u, c);
+      noise_words(P, site, step, 1u, cc);
     }
     const double rho_d = density_sum(f);
     const T rho = (T)rho_d;
-    const T sx = f[1] + f[2], sy = f[3] + f[4], sz = f[5] + f[6];
-    const T Mx = P.a * (f[1] - f[2]);
-    const T My = P.a * (f[3] - f[4]);
-    const T Mz = P.a * (f[5] - f[6]);
-    const T Mn1 = P.b * (sx - sy);
-    const T Mn2 = P.e * ((sx + sy) - (T)2 * sz);
-    const T Ms = fma(P.c1, (sx + sy) + sz, -(P.c0 * f[0]));
-    T x[6] = {0, 0, 0, 0, 0, 0};
+    T X[4] = {0, 0, 0, 0}, XX[4] = {0, 0, 0, 0};
     if (on) {
-      const T sr = fixed ? noise_scale_local(rho) : noise_scale(P, rho);
-      const T gj = sr * P.sq_j, gn = sr * P.sq_n;
-      x[0] = gj * z[0];
-      x[1] = gj * z[1];
-      x[2] = gj * z[2];
-      x[3] = gn * z[3];
-      x[4] = gn * zz[0];
-      x[5] = sr * P.sq_s * zz[1];
+      const T rn = noise_density<T, NP>(P, rho);
+      noise_terms<T, NP>(P, c, rn, P.nA, P.nA, P.nA, P.nB, X);
+      noise_terms<T, NP>(P, cc, rn, P.nE, P.nC, P.nC, P.nC, XX);
     }
-    const T dx = fma(-P.om_j, Mx, x[0]);
-    const T dy = fma(-P.om_j, My, x[1]);
-    const T dz = fma(-P.om_j, Mz, x[2]);
-    const T dn1 = fma(-P.om_n, Mn1, x[3]);
-    const T dn2 = fma(-P.om_n, Mn2, x[4]);
-    const T ds = fma(-P.om_s, Ms, x[5]);
-    const T cx = P.a * dx, cy = P.a * dy, cz = P.a * dz;
-    const T p1 = P.b * dn1, p2 = P.e * dn2, ps = P.c1 * ds;
-    const T hx = (p1 + p2) + ps;
-    const T hy = (p2 - p1) + ps;
-    const T hz = ps - (T)2 * p2;
-    const T f1 = fma(P.w1, hx + cx, f[1]);
-    const T f2 = fma(P.w1, hx - cx, f[2]);
-    const T f3 = fma(P.w1, hy + cy, f[3]);
-    const T f4 = fma(P.w1, hy - cy, f[4]);
-    const T f5 = fma(P.w1, hz + cz, f[5]);
-    const T f6 = fma(P.w1, hz - cz, f[6]);
+    const T sx = f[1] + f[2], sy = f[3] + f[4], sz = f[5] + f[6];
+    const T Cx = fma(-P.kj, f[1] - f[2], X[0]);                      // currents
+    const T Cy = fma(-P.kj, f[3] - f[4], X[1]);
+    const T Cz = fma(-P.kj, f[5] - f[6], X[2]);
+    const T P1 = fma(-P.kn, sx - sy, X[3]);                          // traceless
+    const T P2 = fma(-P.ke, (sx + sy) - (T)2 * sz, XX[0]);
+    const T Ps = fma(-P.ks, (sx + sy) + sz, fma(P.ks0, f[0], XX[1]));  // trace
+    const T Hx = (P1 + P2) + Ps;
+    const T Hy = (P2 - P1) + Ps;
+    const T Hz = Ps - (T)2 * P2;
+    const T f1 = f[1] + (Hx + Cx);
+    const T f2 = f[2] + (Hx - Cx);
+    const T f3 = f[3] + (Hy + Cy);
+    const T f4 = f[4] + (Hy - Cy);
+    const T f5 = f[5] + (Hz + Cz);
+    const T f6 = f[6] + (Hz - Cz);
     f[1] = f1;
     f[2] = f2;
     f[3] = f3;
