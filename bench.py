@@ -295,7 +295,7 @@ def fp64_paths(torch, flb, tune, f64, dims, k64, check):
     for tag, cfg in (("fp64_plain", {"kernel": "plain"}), ("fp64_tuned", tune.best_config(2, 8, dims))):
         P = flb.Lattice(2, dims, precision=8, omega=1.0, seed=0, **cfg)
         P.set_populations(f64)
-        P.step(10)
+        P.step(20)
         spl = steps_per_launch(cfg)
         ms, kern = time_steps(torch, P, k64, 0, spl)
         r, flat = roofline(kernel_name(cfg, prec="double"), kern * 1e3, 2 * 5 * 8 * N, spl, N)
@@ -407,7 +407,7 @@ def main():
     if not args.no_fp64:
         log("fp64 paths")
         f64 = f0.to(torch.float64)
-        out.update(fp64_paths(torch, flb, tune, f64, dims, max(args.steps // 4, 20), not args.no_check))
+        out.update(fp64_paths(torch, flb, tune, f64, dims, max(args.steps // 4, 40), not args.no_check))
         del f64
 
     if not args.no_legs:

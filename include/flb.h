@@ -338,9 +338,12 @@ int flb_gauss_map(int32_t precision, const void* d_words, int64_t n, void* d_z, 
  * one launch per step, or per two steps for D2Q5 members at depth 2; with
  * `workers` > 0 a persistent grid strides over the items), and small D1Q3
  * lattices run whole chunks of steps inside one workgroup's LDS, in a launch
- * of their own on the same stream.  Chunks of `chunk` steps are captured
- * once into a HIP graph and replayed.  Members may be admitted and retired
- * between calls. */
+ * of their own on a second stream of the batch (forked from the batch's
+ * stream at the chunk start and joined before the chunk's step advance, so
+ * it overlaps the other members' passes; in a captured graph, a parallel
+ * branch).  Chunks of `chunk` steps are captured once into a HIP graph and
+ * replayed.  Members may be admitted and retired between calls; flb_batch_sync
+ * (or work ordered after it on the batch's stream) sees every member done. */
 typedef struct {
   int32_t chunk;        /* steps per graph (>= 1); 0 -> 16 */
   int32_t use_graph;    /* 1 = capture chunks in a HIP graph, 0 = eager launches */

@@ -226,6 +226,11 @@ struct flb_batch {
   bool lds_lg;   // every LDS member has local Gaussian noise
   hipGraphExec_t exec;
   int exec_chunk;
+  // the LDS members run on a second stream, forked from and joined to the
+  // batch's stream around the HBM members' passes (in a captured graph: a
+  // parallel branch)
+  hipStream_t side;
+  hipEvent_t ev_fork, ev_join;
 };
 
 namespace {
@@ -361,15 +366,25 @@ int rebuild_t(flb_batch* b) {
 }
 
 template <typename T>
-void enqueue_chunk_t(flb_batch* b, int c) {
+int enqueue_chunk_t(flb_batch* b, int c) {
   const BatchRep<T>* reps = (const BatchRep<T>*)b->d_table;
   hipStream_t st = b->stream;
+  // the LDS members share nothing with the others until the step advance:
+  // with HBM members present they run on the side stream, concurrently
+  bool hbm = false;
+  for (int d = 1; d <= 8; ++d) hbm |= b->nitems[d] > 0;
+  const bool fork = b->nlds > 0 && hbm;
+  if (fork) {
+    HIP_TRY(hipEventRecord(b->ev_fork, st));
+    HIP_TRY(hipStreamWaitEvent(b->side, b->ev_fork, 0));
+  }
   if (b->nlds > 0) {
     const int32_t* lr = (const int32_t*)(b->d_table + b->off_lds);
     const dim3 grid(b->nlds), block(256);
+    hipStream_t ls = fork ? b->side : st;
 #define FLB_LDS(SV)                                                                                  \
-  (b->lds_lg ? (void)(k_batch_lds_d1<T, SV, kPlanLocalGauss><<<grid, block, b->lds_bytes, st>>>(reps, lr, c)) \
-             : (void)(k_batch_lds_d1<T, SV><<<grid, block, b->lds_bytes, st>>>(reps, lr, c)))
+  (b->lds_lg ? (void)(k_batch_lds_d1<T, SV, kPlanLocalGauss><<<grid, block, b->lds_bytes, ls>>>(reps, lr, c)) \
+             : (void)(k_batch_lds_d1<T, SV><<<grid, block, b->lds_bytes, ls>>>(reps, lr, c)))
     switch (b->lds_spt) {
       case 1: FLB_LDS(1); break;
       case 2: FLB_LDS(2); break;
@@ -378,6 +393,7 @@ void enqueue_chunk_t(flb_batch* b, int c) {
       default: FLB_LDS(16); break;
     }
 #undef FLB_LDS
+    if (fork) HIP_TRY(hipEventRecord(b->ev_join, b->side));
   }
   if (b->nitems[7] > 0) {  // depth-2 members: two-step passes, a single flat step for an odd chunk
     const int32_t* ir2 = (const int32_t*)(b->d_table + b->off_items[7][0]);
@@ -443,20 +459,25 @@ void enqueue_chunk_t(flb_batch* b, int c) {
 #undef FLB_BATCH_ROWS
     }
   }
+  if (fork) HIP_TRY(hipStreamWaitEvent(st, b->ev_join, 0));
   k_batch_advance<T><<<(b->nreps + 255) / 256, 256, 0, st>>>((BatchRep<T>*)b->d_table, b->nreps, c);
+  return FLB_OK;
 }
 
-void enqueue_chunk(flb_batch* b, int c) {
-  if (b->precision == 4) enqueue_chunk_t<float>(b, c);
-  else enqueue_chunk_t<double>(b, c);
+int enqueue_chunk(flb_batch* b, int c) {
+  return b->precision == 4 ? enqueue_chunk_t<float>(b, c) : enqueue_chunk_t<double>(b, c);
 }
 
 int capture(flb_batch* b, int c) {
   drop_graph(b);
   hipGraph_t graph = nullptr;
   HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-  enqueue_chunk(b, c);
+  const int rc = enqueue_chunk(b, c);
   hipError_t e = hipStreamEndCapture(b->stream, &graph);
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
   e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
@@ -523,6 +544,18 @@ int flb_batch_create(const flb_batch_opts* opts, flb_batch** out) {
     }
     b->own_stream = true;
   }
+  b->side = nullptr;
+  b->ev_fork = b->ev_join = nullptr;
+  e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);  // default priority
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->side) (void)hipStreamDestroy(b->side);
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return hip_fail(e, "side stream / events");
+  }
   *out = b;
   return FLB_OK;
 }
@@ -582,10 +615,16 @@ int flb_batch_step(flb_batch* b, int64_t nsteps) {
       }
       for (int64_t i = 0; i < chunks; ++i) HIP_TRY(hipGraphLaunch(b->exec, b->stream));
     } else {
-      for (int64_t i = 0; i < chunks; ++i) enqueue_chunk(b, c);
+      for (int64_t i = 0; i < chunks; ++i) {
+        const int rc = enqueue_chunk(b, c);
+        if (rc) return rc;
+      }
     }
   }
-  if (rem) enqueue_chunk(b, rem);
+  if (rem) {
+    const int rc = enqueue_chunk(b, rem);
+    if (rc) return rc;
+  }
   HIP_TRY(hipGetLastError());
   // buffer swaps of each member, chunk by chunk (depth-2 D2Q5 members swap once per pass)
   for (flb_lattice* h : b->members) {
@@ -617,6 +656,10 @@ int flb_batch_destroy(flb_batch* b) {
   for (flb_lattice* h : b->members) h->batch_refs -= 1;
   drop_graph(b);
   if (b->d_table) (void)hipFree(b->d_table);
+  (void)hipStreamSynchronize(b->side);
+  (void)hipEventDestroy(b->ev_fork);
+  (void)hipEventDestroy(b->ev_join);
+  (void)hipStreamDestroy(b->side);
   if (b->own_stream) (void)hipStreamDestroy(b->stream);
   delete b;
   return FLB_OK;
