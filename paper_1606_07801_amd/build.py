@@ -28,6 +28,8 @@ FLAGS = [
     # no packed FP32 instructions in generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
+    # roctx ranges around the API calls (rocprofv3 --marker-trace)
+    "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx",
 ]
 
 

@@ -1019,6 +1019,7 @@ int flb_destroy(flb_lattice* h) {
 }
 
 int flb_set_populations(flb_lattice* h, const void* src, int src_on_device, int64_t step) {
+  flb::TraceRange trace_("flb_set_populations");
   if (!h || !src) return fail(FLB_EINVAL, "NULL argument");
   if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
   if (step < 0) return fail(FLB_EINVAL, "step must be >= 0");
@@ -1051,6 +1052,7 @@ int flb_set_populations(flb_lattice* h, const void* src, int src_on_device, int6
 }
 
 int flb_get_populations(flb_lattice* h, void* dst, int dst_on_device) {
+  flb::TraceRange trace_("flb_get_populations");
   if (!h || !dst) return fail(FLB_EINVAL, "NULL argument");
   if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
   DeviceGuard g(h->device);
@@ -1084,6 +1086,7 @@ int flb_get_populations(flb_lattice* h, void* dst, int dst_on_device) {
 }
 
 int flb_step(flb_lattice* h, int64_t nsteps) {
+  flb::TraceRange trace_("flb_step");
   if (!h) return fail(FLB_EINVAL, "NULL handle");
   if (nsteps < 0) return fail(FLB_EINVAL, "nsteps must be >= 0");
   if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
@@ -1179,6 +1182,7 @@ int flb_get_step(flb_lattice* h, int64_t* step) {
 }
 
 int flb_moments(flb_lattice* h, flb_moments_t* out) {
+  flb::TraceRange trace_("flb_moments");
   if (!h || !out) return fail(FLB_EINVAL, "NULL argument");
   if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
   DeviceGuard g(h->device);
@@ -1203,6 +1207,7 @@ int flb_moments(flb_lattice* h, flb_moments_t* out) {
 }
 
 int flb_structure_factor(flb_lattice* h, const int32_t* kvec, int32_t nk, int32_t mode, double* S_out) {
+  flb::TraceRange trace_("flb_structure_factor");
   if (!h) return fail(FLB_EINVAL, "NULL handle");
   if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
   if (mode < 0 || mode > 3) return fail(FLB_EINVAL, "unknown mode %d", mode);
@@ -1280,6 +1285,7 @@ int flb_set_moment_sampling(flb_lattice* h, int64_t every) {
 }
 
 int flb_sampled_moments(flb_lattice* h, flb_moments_t* sum, int64_t* nsamples) {
+  flb::TraceRange trace_("flb_sampled_moments");
   if (!h || !sum || !nsamples) return fail(FLB_EINVAL, "NULL argument");
   if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
   DeviceGuard g(h->device);
@@ -1365,6 +1371,7 @@ int flb_set_correlation(flb_lattice* h, int64_t every, const int32_t* kvec, int3
 }
 
 int flb_correlation(flb_lattice* h, double* sij, double* ct, int64_t* nsamples) {
+  flb::TraceRange trace_("flb_correlation");
   if (!h || !nsamples) return fail(FLB_EINVAL, "NULL argument");
   if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
   if (!h->corr_mem) return fail(FLB_ESTATE, "no correlation sampling was set up");
@@ -1383,6 +1390,7 @@ int flb_correlation(flb_lattice* h, double* sij, double* ct, int64_t* nsamples) 
 }
 
 int flb_fourier_amplitudes(flb_lattice* h, double* amp) {
+  flb::TraceRange trace_("flb_fourier_amplitudes");
   if (!h) return fail(FLB_EINVAL, "NULL handle");
   if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
   if (!h->corr_mem) return fail(FLB_ESTATE, "no correlation k-list was set up");
@@ -1440,6 +1448,7 @@ int flb_set_regions(flb_lattice* h, const uint8_t* region, int32_t nregions, con
 }
 
 int flb_profile(flb_lattice* h, int32_t axis, double* sum_rho, double* sum_rho2) {
+  flb::TraceRange trace_("flb_profile");
   if (!h || !sum_rho || !sum_rho2) return fail(FLB_EINVAL, "NULL argument");
   if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
   if (axis < 0 || axis >= h->d) return fail(FLB_EINVAL, "axis %d outside [0, %d)", axis, h->d);
@@ -1465,6 +1474,7 @@ int flb_profile(flb_lattice* h, int32_t axis, double* sum_rho, double* sum_rho2)
 }
 
 int flb_profile_noalloc(flb_lattice* h, int32_t axis, double* d_sum_rho, double* d_sum_rho2) {
+  flb::TraceRange trace_("flb_profile_noalloc");
   if (!h || !d_sum_rho || !d_sum_rho2) return fail(FLB_EINVAL, "NULL argument");
   if (h->batch_refs > 0) return fail(FLB_ESTATE, "lattice is a member of a batch");
   if (axis < 0 || axis >= h->d) return fail(FLB_EINVAL, "axis %d outside [0, %d)", axis, h->d);
@@ -1482,6 +1492,7 @@ int flb_profile_noalloc(flb_lattice* h, int32_t axis, double* d_sum_rho, double*
 }
 
 int flb_sync(flb_lattice* h) {
+  flb::TraceRange trace_("flb_sync");
   if (!h) return fail(FLB_EINVAL, "NULL handle");
   DeviceGuard g(h->device);
   HIP_TRY(hipStreamSynchronize(h->stream));

@@ -595,6 +595,7 @@ int flb_batch_retire(flb_batch* b, flb_lattice* h) {
 }
 
 int flb_batch_step(flb_batch* b, int64_t nsteps) {
+  flb::TraceRange trace_("flb_batch_step");
   if (!b) return fail(FLB_EINVAL, "NULL batch");
   if (nsteps < 0) return fail(FLB_EINVAL, "nsteps must be >= 0");
   if (b->members.empty() || nsteps == 0) return FLB_OK;
@@ -643,6 +644,7 @@ int flb_batch_size(flb_batch* b, int32_t* n) {
 }
 
 int flb_batch_sync(flb_batch* b) {
+  flb::TraceRange trace_("flb_batch_sync");
   if (!b) return fail(FLB_EINVAL, "NULL batch");
   DevGuard g(b->device);
   HIP_TRY(hipStreamSynchronize(b->stream));

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <string>
 #include <vector>
@@ -94,6 +95,15 @@ struct flb_lattice {
 };
 
 namespace flb {
+
+// A roctx range around one API call (host side: the call's enqueue time;
+// rocprofv3 --marker-trace records it beside the kernels it launched).
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 extern thread_local std::string g_err;
 int fail(int code, const char* fmt, ...);

@@ -32,6 +32,18 @@ def test_library_exports_every_declared_symbol():
     assert set(declared) == set(flb.EXPORTS)
 
 
+def test_api_calls_carry_roctx_ranges():
+    # the API calls mark their host-side extent with roctx ranges: the
+    # library imports the range API (recorded by rocprofv3 --marker-trace)
+    import subprocess
+    out = subprocess.run(["nm", "-D", flb.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    undefined = {ln.split()[-1] for ln in out.splitlines() if " U " in ln}
+    assert {"roctxRangePushA", "roctxRangePop"} <= undefined
+    src = open(os.path.join(ROOT, "paper_1606_07801_amd", "csrc", "flb.hip")).read()
+    for name in ("flb_step", "flb_set_populations", "flb_get_populations", "flb_structure_factor"):
+        assert f'TraceRange trace_("{name}")' in src, name
+
+
 def test_version_and_constants():
     lib = flb.load()
     assert lib.flb_version() == 1
