@@ -45,10 +45,18 @@ __device__ __forceinline__ int member_parity(const BatchRep<T>& R, int k) {
 // rows; taller items spread the item's descriptor loads over more sites.
 constexpr int kBatchTX = 256;
 constexpr int kBatchRY = 2;
+// Flat work items: rows of 256 sites per lane and the store kind per model.
+// D3Q7 members take one row and ordinary (cached) stores: at the member
+// sizes of an ensemble or a request stream (up to ~1e8 sites) that measured
+// 35 against 47 us per step at 153^3 and 622 against 703 us at 390^3
+// (two rows, non-temporal stores); the others keep two rows and
+// non-temporal stores, as fast either way.
+template <int D> constexpr int kFlatRY = D == 3 ? 1 : 2;
+template <int D> constexpr bool kFlatNT = D != 3;
 
 // Work list: item w is tile item_tile[w] of member item_rep[w]; with a grid
 // smaller than the list the workgroups persist and stride over it.
-// Flat work list: item w covers sites item_tile[w] * 256 * kBatchRY ... of
+// Flat work list: item w covers sites item_tile[w] * 256 * kFlatRY<D> ... of
 // member item_rep[w] (flat_tile), so narrow lattices keep every lane busy.
 template <int D, typename T, int NP = kPlanRuntime>
 __global__ void __launch_bounds__(256) k_batch_flat(const BatchRep<T>* __restrict__ reps,
@@ -64,14 +72,16 @@ __global__ void __launch_bounds__(256) k_batch_flat(const BatchRep<T>* __restric
     const int par = member_parity(R, k);
     if (R.aa) {  // in place, from the form of this step's parity
       if (par == 0)
-        flat_tile_aa<D, T, kBatchRY, true, kFormAAC, NP>((T*)R.pop, P, step, tile * 256 * kBatchRY, threadIdx.x);
+        flat_tile_aa<D, T, kFlatRY<D>, kFlatNT<D>, kFormAAC, NP>((T*)R.pop, P, step, tile * 256 * kFlatRY<D>,
+                                                                 threadIdx.x);
       else
-        flat_tile_aa<D, T, kBatchRY, true, kFormAAS, NP>((T*)R.pop, P, step, tile * 256 * kBatchRY, threadIdx.x);
+        flat_tile_aa<D, T, kFlatRY<D>, kFlatNT<D>, kFormAAS, NP>((T*)R.pop, P, step, tile * 256 * kFlatRY<D>,
+                                                                 threadIdx.x);
       continue;
     }
     const T* g = (const T*)(R.pop + par * R.plane);
     T* h = (T*)(R.pop + (par ^ 1) * R.plane);
-    flat_tile<D, T, kBatchRY, true, NP>(g, h, P, step, tile * 256 * kBatchRY, threadIdx.x);
+    flat_tile<D, T, kFlatRY<D>, kFlatNT<D>, NP>(g, h, P, step, tile * 256 * kFlatRY<D>, threadIdx.x);
   }
 }
 
@@ -318,7 +328,8 @@ int rebuild_t(flb_batch* b) {
     }
     R.depth = 1;
     if (flat) R.tiles_x = -1;  // marks a flat member
-    const int64_t ntile = flat ? (h->n + 256 * kBatchRY - 1) / (256 * kBatchRY)
+    const int64_t fry = h->d == 3 ? kFlatRY<3> : kFlatRY<1>;
+    const int64_t ntile = flat ? (h->n + 256 * fry - 1) / (256 * fry)
                                : R.tiles_x * ((R.nrows + item_rows - 1) / item_rows);
     if (ntile >= (1ll << 31)) return fail(FLB_EINVAL, "member %d has too many tiles", i);
     const int cls = h->d + (flat ? 3 : 0);
