@@ -3,7 +3,8 @@ Sanitizer, on the CPU: the C client (compiled with the same clang
 sanitizers, leak detection on) and the host-side ABI tests (a Python
 process with the ASan runtime preloaded) against lib/libflb_san.so, built by
 `python -m paper_1606_07801_amd.build --sanitize` (device code as usual,
-sanitizers on the host side only).  Skipped when that build is absent."""
+sanitizers on the host side only).  Skipped when that build is absent or
+older than the sources."""
 
 import os
 import subprocess
@@ -16,9 +17,20 @@ from paper_1606_07801_amd import build
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CLANG = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "llvm", "bin", "clang")
 
-pytestmark = pytest.mark.skipif(not os.path.exists(build.LIB_SAN) or build.sanitizer_runtime() is None
-                                or not os.path.exists(CLANG),
-                                reason="no sanitized build (python -m paper_1606_07801_amd.build --sanitize)")
+def _stale():
+    """The sanitized build predates a source it is built from."""
+    srcs = [os.path.join(build.CSRC, f) for f in os.listdir(build.CSRC)] + [os.path.join(ROOT, "include", "flb.h")]
+    return os.path.getmtime(build.LIB_SAN) < max(os.path.getmtime(f) for f in srcs)
+
+
+pytestmark = [
+    pytest.mark.skipif(not os.path.exists(build.LIB_SAN) or build.sanitizer_runtime() is None
+                       or not os.path.exists(CLANG),
+                       reason="no sanitized build (python -m paper_1606_07801_amd.build --sanitize)"),
+    pytest.mark.skipif(os.path.exists(build.LIB_SAN) and _stale(),
+                       reason="the sanitized build is older than the sources; rebuild it with "
+                              "python -m paper_1606_07801_amd.build --sanitize"),
+]
 
 
 def test_c_client_under_asan_ubsan(tmp_path):
