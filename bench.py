@@ -360,8 +360,9 @@ def main():
     t0 = (-args.warmup) % se if se else 0
     L.set_populations(f0, step=t0)
     kvecs = [(k, 0) for k in range(1, 513)] + [(0, k) for k in range(1, 513)]
-    if se:
+    if se:  # S(k) and the lattice sums (FP64 accumulators) of the state every se steps
         L.set_sampling(se, kvecs)
+        L.set_moment_sampling(se)
 
     # warmup, then the timed region (all hot-path rows: step + sampled stats)
     log(f"headline: D2Q5 {n}^2 fp32 {cfg}, warmup {args.warmup}, timed {args.steps}")
@@ -371,6 +372,7 @@ def main():
     ms_step, kern_ms = time_steps(torch, L, args.steps, se, spl)
     m = L.moments()
     S = L.structure_factor(None, mode="read")[:len(kvecs)] if se else None
+    msum, nmom = L.sampled_moments() if se else (None, 0)
     L.close()
 
     value = N / (ms_step * 1e-3) / 1e6  # MLUPS of the whole job
@@ -383,7 +385,7 @@ def main():
         "config": {
             "workload": f"D2Q5 {n}x{n} periodic, fp32 populations, rho=10 sine mode 0.1 plus equilibrium "
                         f"(Poisson) noise, omega=1.0, local Gaussian noise (Philox), S(k) of 1024 axis modes "
-                        f"accumulated every {se} steps, lattice sums at the end",
+                        f"and the lattice sums accumulated every {se} steps",
             "kernel": cfg, "sites": N, "step0": t0,
         },
         "roofline": rl,
@@ -393,6 +395,11 @@ def main():
     if se:
         times = [t - t0 for t in range(t0, t_start + args.steps) if t % se == 0]
         out["sk_flat"] = sk_flatness(S, kvecs, n, m["sum_rho_pos"] / N, times, {(1, 0)})
+        # the sampled lattice sums: mean site variance of rho over the samples
+        # (Poisson equilibrium: rho-bar; the sine mode adds its own variance)
+        out["moment_samples"] = nmom
+        if nmom:
+            out["mean_var_rho"] = round(msum["sum_rho2"] / (nmom * N) - (msum["mass"] / (nmom * N)) ** 2, 4)
 
     log("depth-1 reference")
     depth1, D1 = depth1_reference(torch, flb, f0, dims)
@@ -540,21 +547,29 @@ def leg_d3q7(torch, flb, tune, args, check=True):
     cfg = tune.best_config(3, 4, dims)
     f0 = d3q7_state(torch, flb)
     L = flb.Lattice(3, dims, precision=4, omega=1.2, seed=0, **cfg)
-    L.set_populations(f0)
+    se = args.sample_every
+    L.set_populations(f0, step=(-args.warmup) % se if se else 0)
+    if se:  # S(k) of the 768 axis modes and the lattice sums every se steps
+        L.set_sampling(se, [(k, 0, 0) for k in range(1, 257)] + [(0, k, 0) for k in range(1, 257)]
+                       + [(0, 0, k) for k in range(1, 257)])
+        L.set_moment_sampling(se)
     L.step(args.warmup)
     steps = max(args.steps, 100)
     spl = steps_per_launch(cfg)
     steps -= steps % spl
-    ms, kern = time_steps(torch, L, steps, 0, spl)
+    ms, kern = time_steps(torch, L, steps, se, spl)
     r, flat = roofline(kernel_name(cfg, d=3), kern * 1e3, 2 * 7 * 4 * N, spl, N)
     m = L.moments()
-    out = {"workload": "D3Q7 512^3 fp32 rho=5+sqrt(5)z, omega=1.2", "kernel": cfg, "steps": steps,
+    out = {"workload": f"D3Q7 512^3 fp32 rho=5+sqrt(5)z, omega=1.2, S(k) of 768 axis modes and the lattice sums "
+                       f"every {se} steps", "kernel": cfg, "steps": steps,
            "ms_per_step": round(ms, 4), "mlups": round(N / (ms * 1e-3) / 1e6, 1),
            "effective_gbs": flat["effective_gbs"], "hbm_frac_measured": flat["hbm_frac_measured"],
            "valu_frac": flat["valu_frac"], "roofline": r,
            "mass_drift_rel": (m["mass"] - m["mass0"]) / m["mass0"]}
     if check:
         log("D3Q7 oracle check")
+        L.set_sampling(0)
+        L.set_moment_sampling(0)
         L.set_populations(f0)
         L.step(4)
         out["oracle"] = sampled_error(L.get_populations(), f0.cpu().numpy(), 3, 1.2, 4, 5.0)

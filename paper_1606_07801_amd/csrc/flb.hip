@@ -325,7 +325,8 @@ void launch_convert(flb_lattice* h, bool to_canon, const void* src, void* dst, i
 // lattice sums into work.red_out (device)
 template <int D, typename T>
 void launch_moments_t(flb_lattice* h, const T* g) {
-  const int64_t nb = std::min<int64_t>((h->n + 255) / 256, kRedBlocks);
+  const int64_t units = h->p.n[1] * h->p.n[2] * ((h->p.n[0] + kMomSeg<D> - 1) / kMomSeg<D>);
+  const int64_t nb = std::min<int64_t>(units, kRedBlocks);
   double* part = (double*)(h->work + h->wl.red_part);
   double* out = (double*)(h->work + h->wl.red_out);
   k_moments_partial<D, T><<<(unsigned)nb, 256, 0, h->stream>>>(g, h->p.n[0], h->p.n[1], h->p.n[2], part,
