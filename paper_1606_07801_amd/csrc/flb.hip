@@ -329,8 +329,12 @@ void launch_moments_t(flb_lattice* h, const T* g) {
   const int64_t nb = std::min<int64_t>(units, kRedBlocks);
   double* part = (double*)(h->work + h->wl.red_part);
   double* out = (double*)(h->work + h->wl.red_out);
-  k_moments_partial<D, T><<<(unsigned)nb, 256, 0, h->stream>>>(g, h->p.n[0], h->p.n[1], h->p.n[2], part,
-                                                                state_form(h));
+  // pull-form states under 4 GiB take the buffer-resource loads
+  if (state_form(h) == kFormPull && h->plane < (1ull << 32) && (int64_t)h->Q * h->n * (int64_t)h->s < (1ll << 32))
+    k_moments_partial<D, T, true><<<(unsigned)nb, 256, 0, h->stream>>>(g, h->p.n[0], h->p.n[1], h->p.n[2], part);
+  else
+    k_moments_partial<D, T><<<(unsigned)nb, 256, 0, h->stream>>>(g, h->p.n[0], h->p.n[1], h->p.n[2], part,
+                                                                  state_form(h));
   k_moments_final<<<kNV, 256, 0, h->stream>>>(part, (int)nb, out);
 }
 

@@ -39,7 +39,9 @@ constexpr int kNV = 40;
 // one, 78 against 85 us for D2Q5 with two).
 template <int D> constexpr int kMomSeg = 256 * (D == 3 ? 2 : 4);
 
-template <int D, typename T>
+// BUF: the pull form of a state under 4 GiB, loaded through a buffer
+// resource (32-bit lane offsets, row and plane offsets in scalar registers).
+template <int D, typename T, bool BUF = false>
 __global__ void __launch_bounds__(256) k_moments_partial(const T* __restrict__ g, int64_t nx,
                                                          int64_t ny, int64_t nz,
                                                          double* __restrict__ part, int form = kFormPull) {
@@ -65,12 +67,43 @@ __global__ void __launch_bounds__(256) k_moments_partial(const T* __restrict__ g
     const int64_t y = r % ny, z = r / ny;
     T fv[SUB][Q];
     bool ok[SUB];
+    if constexpr (BUF) {
+      constexpr uint32_t S = sizeof(T);
+      const uint32_t nS = (uint32_t)n * S;
+      const __amdgpu_buffer_rsrc_t rg = buf_rsrc(g, (uint32_t)Q * nS);
+      const uint32_t ux = (uint32_t)nx, uy = (uint32_t)ny, uz = (uint32_t)nz;
+      const uint32_t yy = (uint32_t)y, zz = (uint32_t)z;
+      const uint32_t ym = yy == 0 ? uy - 1 : yy - 1, yp = yy == uy - 1 ? 0 : yy + 1;
+      const uint32_t zm = zz == 0 ? uz - 1 : zz - 1, zp = zz == uz - 1 ? 0 : zz + 1;
+      const uint32_t row = ux * (yy + uy * zz) * S;  // uniform byte offsets of the rows
+      const uint32_t rym = ux * (ym + uy * zz) * S, ryp = ux * (yp + uy * zz) * S;
+      const uint32_t rzm = ux * (yy + uy * zm) * S, rzp = ux * (yy + uy * zp) * S;
 #pragma unroll
-    for (int j = 0; j < SUB; ++j) {
-      const int64_t x = x0 + j * 256 + threadIdx.x;
-      ok[j] = x < nx;
-      const Nbr b = neighbours(ok[j] ? x : nx - 1, y, z, nx, ny, nz);
-      gather<D, T>(g, n, b, fv[j], form);
+      for (int j = 0; j < SUB; ++j) {
+        const int64_t x = x0 + j * 256 + threadIdx.x;
+        ok[j] = x < nx;
+        const uint32_t xs = ok[j] ? (uint32_t)x : ux - 1;
+        const uint32_t vx = xs * S, vxm = (xs == 0 ? ux - 1 : xs - 1) * S, vxp = (xs == ux - 1 ? 0 : xs + 1) * S;
+        fv[j][0] = buf_ld<T>(rg, vx, row);
+        fv[j][1] = buf_ld<T>(rg, vxm, nS + row);
+        fv[j][2] = buf_ld<T>(rg, vxp, 2 * nS + row);
+        if constexpr (D >= 2) {
+          fv[j][3] = buf_ld<T>(rg, vx, 3 * nS + rym);
+          fv[j][4] = buf_ld<T>(rg, vx, 4 * nS + ryp);
+        }
+        if constexpr (D >= 3) {
+          fv[j][5] = buf_ld<T>(rg, vx, 5 * nS + rzm);
+          fv[j][6] = buf_ld<T>(rg, vx, 6 * nS + rzp);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < SUB; ++j) {
+        const int64_t x = x0 + j * 256 + threadIdx.x;
+        ok[j] = x < nx;
+        const Nbr b = neighbours(ok[j] ? x : nx - 1, y, z, nx, ny, nz);
+        gather<D, T>(g, n, b, fv[j], form);
+      }
     }
 #pragma unroll
     for (int j = 0; j < SUB; ++j) {
