@@ -182,6 +182,43 @@ def test_d2q5_planes_beyond_4_gib():
 
 
 @pytest.mark.parametrize("precision", [4, 8])
+def test_d2q5_4096_sampled_statistics(precision):
+    # the lattice sums and the S(k) of 1024 axis modes as the benchmark
+    # samples them (every 10 steps, the tuned two-step pass with its fused
+    # density partials), on the first sampled state -- the seeded state
+    # itself -- against the oracle's FP64 sums and FFT of that state
+    d, dims = 2, (4096, 4096)
+    lat = oracle.make_lattice(d)
+    f0 = inputs.poisson_counts(dims, 10.0 * lat.w, seed=11).astype(np.float32 if precision == 4 else np.float64)
+    cfg = tune.best_config(d, precision, dims)
+    assert cfg["kernel"] == "two"
+    L = gpu_lattice(d, dims, precision, omega=1.0, seed=0, **cfg)
+    L.set_populations(f0, step=0)
+    L.set_sampling(10, KVECS)
+    L.set_moment_sampling(10)
+    L.step(10)
+    msum, nmom = L.sampled_moments()
+    S = L.structure_factor(None, mode="read")[:len(KVECS)]
+    L.close()
+    assert nmom == 1
+    s = oracle.lattice_sums(f0)
+    rel = lambda a, b: abs(a - b) / max(abs(b), 1.0)
+    tol = 1e-13
+    assert rel(msum["mass"], s["mass"]) < tol
+    assert np.abs(msum["sum_f"] - s["sum_f"]).max() < tol * s["mass"]
+    assert np.abs(msum["sum_ff"] - s["sum_ff"]).max() < tol * s["sum_rho2"]
+    assert rel(msum["sum_rho2"], s["sum_rho2"]) < tol
+    assert rel(msum["sum_rho_pos"], s["sum_rho_pos"]) < tol
+    assert msum["n_negative"] == s["n_negative"] and msum["nonfinite"] == 0
+    rho = f0.astype(np.float64).sum(axis=0)
+    ref = oracle.structure_factor(rho, KVECS, method="fft")
+    err = np.abs(S - ref) / np.maximum(ref, rho.mean())
+    print(f"[stats] D2Q5 4096^2 fp{8 * precision}: lattice sums vs oracle max rel "
+          f"{rel(msum['sum_rho2'], s['sum_rho2']):.2e}, S(k) max err {err.max():.3e}", flush=True)
+    assert err.max() < 1e-10
+
+
+@pytest.mark.parametrize("precision", [4, 8])
 def test_d2q5_4096_low_density(precision):
     # rho = 0.1.  FP64: one pass of the tuned two-step kernel against the
     # oracle.  FP32: the second step of a pass starts from rounded values, and
