@@ -271,6 +271,43 @@ def test_d3q7_512_gaussian_fp32():
     L.close()
 
 
+def test_d3q7_512_sampled_statistics():
+    # the D3Q7 leg's sampling (768 axis modes and the lattice sums every 10
+    # steps; the sampled step is the row kernel with fused density partials)
+    # on its first sample, the seeded state, against the oracle's FP64 sums
+    # and FFT of that state
+    d, dims = 3, (512, 512, 512)
+    lat = oracle.make_lattice(d)
+    rho = inputs.gaussian_field(dims, 5.0, np.sqrt(5.0), seed=0)
+    f0 = inputs.outer(lat.w, rho).astype(np.float32)
+    del rho
+    kv = [(k, 0, 0) for k in range(1, 257)] + [(0, k, 0) for k in range(1, 257)] + [(0, 0, k) for k in range(1, 257)]
+    L = gpu_lattice(d, dims, 4, omega=1.2, seed=0, **tune.best_config(d, 4, dims))
+    L.set_populations(f0, step=0)
+    L.set_sampling(10, kv)
+    L.set_moment_sampling(10)
+    L.step(10)
+    msum, nmom = L.sampled_moments()
+    S = L.structure_factor(None, mode="read")[:len(kv)]
+    L.close()
+    assert nmom == 1
+    s = oracle.lattice_sums(f0)
+    rel = lambda a, b: abs(a - b) / max(abs(b), 1.0)
+    assert rel(msum["mass"], s["mass"]) < 1e-13
+    assert np.abs(msum["sum_f"] - s["sum_f"]).max() < 1e-13 * abs(s["mass"])
+    assert np.abs(msum["sum_ff"] - s["sum_ff"]).max() < 1e-13 * s["sum_rho2"]
+    assert rel(msum["sum_rho2"], s["sum_rho2"]) < 1e-13
+    assert rel(msum["sum_rho_pos"], s["sum_rho_pos"]) < 1e-13
+    assert msum["n_negative"] == s["n_negative"] > 0
+    rho = f0.astype(np.float64).sum(axis=0)
+    del f0
+    ref = oracle.structure_factor(rho, kv, method="fft")
+    err = np.abs(S - ref) / np.maximum(ref, abs(rho.mean()))
+    print(f"[stats] D3Q7 512^3 fp32: lattice sums vs oracle max rel {rel(msum['sum_rho2'], s['sum_rho2']):.2e}, "
+          f"S(k) max err {err.max():.3e}", flush=True)
+    assert err.max() < 1e-10
+
+
 def test_d1q3_256_fp64_full_run():
     # the D1Q3 workload in full: 10^4 steps, Poisson counts, every population
     d, dims, steps = 1, (256,), 10_000
