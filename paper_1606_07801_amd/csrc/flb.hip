@@ -684,7 +684,7 @@ void axis_sk(flb_lattice* h, int set, int64_t nchunk, bool mx_ready) {
   const double* tw = (const double*)(w + h->wl.tw);
   if (!mx_ready) k_marginal_x<<<(unsigned)((nx + 63) / 64), 256, 0, st>>>(colpart, nchunk, nx, mx);
   // with one plane the row sums are the y marginal
-  if (nz > 1) k_marginal_y<<<(unsigned)((ny + 255) / 256), 256, 0, st>>>(rowsum, ny, nz, my);
+  if (nz > 1) k_marginal_y<<<(unsigned)ny, 256, 0, st>>>(rowsum, ny, nz, my);
   if (h->d == 3) k_marginal_z<<<(unsigned)nz, 256, 0, st>>>(rowsum, ny, mz);
   // an axis-only accumulator list is accumulated here (sk_accumulate skips it)
   double* acc = set == 1 && h->ngen[1] == 0 ? (double*)(w + h->wl.skacc) : nullptr;

@@ -234,14 +234,17 @@ __global__ void __launch_bounds__(256) k_marginal_x(const double* __restrict__ c
   if (grp == 0 && x < nx) mx[x] = ((part[0][lx] + part[1][lx]) + part[2][lx]) + part[3][lx];
 }
 
-// my[y] = sum_z rowsum[y + ny z] (one thread per y).
-__global__ void k_marginal_y(const double* __restrict__ rowsum, int64_t ny, int64_t nz,
-                             double* __restrict__ my) {
-  const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (y >= ny) return;
+// my[y] = sum_z rowsum[y + ny z]: one block per y, thread t adding
+// z = t, t + 256, ... in order, then the block's fixed tree (a thread per y
+// summing all of z in order left a 512^3 lattice two blocks: 126 us).
+__global__ void __launch_bounds__(256) k_marginal_y(const double* __restrict__ rowsum, int64_t ny, int64_t nz,
+                                                    double* __restrict__ my) {
+  __shared__ double lds[4];
+  const int64_t y = blockIdx.x;
   double acc = 0;
-  for (int64_t z = 0; z < nz; ++z) acc += rowsum[y + ny * z];
-  my[y] = acc;
+  for (int64_t z = threadIdx.x; z < nz; z += blockDim.x) acc += rowsum[y + ny * z];
+  acc = block_sum256(acc, lds);
+  if (threadIdx.x == 0) my[y] = acc;
 }
 
 // The reductions after a sampled pass, in one launch of 1024-thread blocks.
