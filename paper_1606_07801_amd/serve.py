@@ -6,9 +6,10 @@ a request is admitted as soon as its device memory (populations + workspace,
 from flb_required_bytes) fits in the HBM budget, joins the running batch at
 the next tick, and is retired when it has done its steps; its final
 statistics are read and its memory released, which lets queued requests in.
-Every tick advances all active lattices by the same number of steps in one
-batched launch, so work of requests that arrived at different times
-overlaps on the device.  Because the batch is bit-identical to stepping
+Every tick advances all active lattices by the same number of steps in
+batched launches (at least tick_steps, as many more as fit a wall-time
+budget at the measured rate, never past the earliest completion), so work
+of requests that arrived at different times overlaps on the device.  Because the batch is bit-identical to stepping
 each lattice alone, a request's result does not depend on what it was
 batched with.
 
@@ -130,7 +131,8 @@ def finish_request(req):
 class Server:
     """Admission by HBM budget, continuous batching by ticks."""
 
-    def __init__(self, budget_bytes=None, tick_steps=64, chunk=None, use_graph=True, device=None, layout="auto"):
+    def __init__(self, budget_bytes=None, tick_steps=64, chunk=None, use_graph=True, device=None, layout="auto",
+                 tick_ms=20.0):
         import torch
         self.torch = torch
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -140,6 +142,11 @@ class Server:
         self.budget = int(budget_bytes)
         self.used = 0
         self.tick_steps = int(tick_steps)
+        # a tick runs at least tick_steps steps and as many more as fit
+        # tick_ms of wall time at the batch's measured rate (admission waits
+        # at most about that long; each tick ends with a synchronisation)
+        self.tick_ms = float(tick_ms)
+        self._step_s = None        # wall seconds per batch step, measured on the current members
         from . import tune
         bcfg = tune.batch_config()
         if chunk is not None:
@@ -186,11 +193,13 @@ class Server:
                 continue
             self.batch.admit(req.lat)
             self.active.append(req)
+            self._step_s = None
 
     def _retire(self, req, now):
         if req in self.active:
             self.active.remove(req)
             self.batch.retire(req.lat)
+            self._step_s = None
         finish_request(req)
         self.used -= req.bytes
         req.done = now
@@ -201,9 +210,14 @@ class Server:
         self._admit(now)
         if not self.active:
             return 0
-        n = min(self.tick_steps, min(r.remaining for r in self.active))
+        left = min(r.remaining for r in self.active)
+        n = min(self.tick_steps, left)
+        if self.tick_ms > 0 and self._step_s:
+            n = min(left, max(n, int(self.tick_ms * 1e-3 / self._step_s)))
+        t0 = time.perf_counter()
         self.batch.step(n)
         self.batch.sync()
+        self._step_s = (time.perf_counter() - t0) / n
         self.ticks += 1
         self.peak_active = max(self.peak_active, len(self.active))
         self.active_ticks += len(self.active)
@@ -273,7 +287,8 @@ def main():
     ap.add_argument("--max-sites", type=float, default=1e8)
     ap.add_argument("--max-steps", type=float, default=1e5)
     ap.add_argument("--budget-gb", type=float, default=0.0)
-    ap.add_argument("--tick", type=int, default=64)
+    ap.add_argument("--tick", type=int, default=64, help="least steps per tick")
+    ap.add_argument("--tick-ms", type=float, default=20.0, help="wall-time budget of a tick (0: tick steps only)")
     ap.add_argument("--layout", default="auto", choices=["auto", "aa", "two"])
     args = ap.parse_args()
     import torch
@@ -281,7 +296,7 @@ def main():
     reqs = make_requests(args.requests, args.rate, args.seed, sites=(1e3, args.max_sites),
                          steps=(1e2, args.max_steps))
     S = Server(budget_bytes=int(args.budget_gb * 2 ** 30) if args.budget_gb else None, tick_steps=args.tick,
-               layout=args.layout)
+               layout=args.layout, tick_ms=args.tick_ms)
     mk = S.run(reqs)
     out = summary(S, mk)
     out.update({"rate_per_s": args.rate, "work_site_updates": S.site_updates,
