@@ -218,6 +218,33 @@ def test_d2q5_4096_sampled_statistics(precision):
     assert err.max() < 1e-10
 
 
+def test_d2q5_4096_structure_factor_flat():
+    # equilibrium from the start: independent Poisson counts at rho 10 give
+    # S(k) = rho for every k != 0, a stationary value of the dynamics (local
+    # noise, unit rates).  1024 axis modes sampled every 10 steps for 600
+    # steps in the benchmark's launch configuration; per mode the z-score of
+    # the sample mean against its standard deviation for correlated samples
+    # (autocorrelation lambda(k)^(2 dt)).
+    import bench
+    d, dims, rho = 2, (4096, 4096), 10.0
+    lat = oracle.make_lattice(d)
+    f0 = inputs.poisson_counts(dims, rho * lat.w, seed=21).astype(np.float32)
+    L = gpu_lattice(d, dims, 4, omega=1.0, seed=5, **tune.best_config(d, 4, dims))
+    L.set_populations(f0, step=0)
+    del f0
+    L.set_sampling(10, KVECS)
+    L.step(600)
+    S = L.structure_factor(None, mode="read")[:len(KVECS)]
+    m = L.moments()
+    L.close()
+    r = bench.sk_flatness(S, KVECS, 4096, m["sum_rho_pos"] / m["nsite"], list(range(0, 600, 10)), set())
+    print(f"[flat] D2Q5 4096^2 fp32, 60 samples: {r}", flush=True)
+    assert r["modes"] == 1024 and r["samples"] == 60
+    assert abs(r["mean_ratio"] - 1.0) < 0.03
+    assert 0.8 < r["mean_z2"] < 1.25
+    assert r["max_abs_z"] < 7.0
+
+
 @pytest.mark.parametrize("precision", [4, 8])
 def test_d2q5_4096_low_density(precision):
     # rho = 0.1.  FP64: one pass of the tuned two-step kernel against the
